@@ -1,0 +1,57 @@
+"""Every plausible mistake planted in a copy of the oracle must trip at least
+one pin.  Each mutant is the oracle's C source with one textual edit (a wrong
+sign, a dropped term, a transposed operand, a wrong index), compiled with the
+oracle's own flags into a temporary library; the pins then run against it.
+Planted mistakes live only in these temporary copies, on the CPU."""
+import os
+
+import pytest
+
+import oracle
+import pins
+
+MUTATIONS = {
+    "update_sign": ("y[i] = y[i] - colk[i] * xk", "y[i] = y[i] + colk[i] * xk"),
+    "dropped_alpha": ("y[i] = alpha * y[i];", "y[i] = y[i];"),
+    "transposed_L": ("y[i] = y[i] - colk[i] * xk", "y[i] = y[i] - A[k + i * lda] * xk"),
+    "skipped_subdiagonal": ("for (int64_t i = k + 1; i < m; ++i) y[i] = y[i] - colk[i] * xk;",
+                            "for (int64_t i = k + 2; i < m; ++i) y[i] = y[i] - colk[i] * xk;"),
+    "wrong_diag_index": ("y[k] = y[k] / A[k + k * lda];", "y[k] = y[k] / A[k + (k > 0 ? k - 1 : 0) * lda + (k > 0)];"),
+    "diag_multiplied": ("y[k] = y[k] / A[k + k * lda];", "y[k] = y[k] * A[k + k * lda];"),
+    "unit_diag_read": ("if (!unit) y[k] = y[k] / A[k + k * lda];", "y[k] = y[k] / A[k + k * lda];"),
+    "alpha_zero_reads_inputs": ("    if (alpha == 0.0) {\n        for (int64_t j = 0; j < n; ++j)\n            for (int64_t i = 0; i < m; ++i) B[i + j * ldb] = 0.0;\n        return;\n    }\n#pragma omp parallel for schedule(dynamic, 1)\n    for (int64_t j = 0; j < n; ++j)\n        d_solve_column",
+                                "#pragma omp parallel for schedule(dynamic, 1)\n    for (int64_t j = 0; j < n; ++j)\n        d_solve_column"),
+    "complex_mul_sign": ("*cr = ar * br - ai * bi;", "*cr = ar * br + ai * bi;"),
+    "complex_mul_swap": ("*ci = ar * bi + ai * br;", "*ci = ar * br + ai * bi;"),
+    "complex_div_conj": ("const double ni = xi * dr - xr * di;", "const double ni = xi * dr + xr * di;"),
+    "complex_div_modulus": ("const double den = dr * dr + di * di;", "const double den = dr * dr - di * di;"),
+    "complex_update_imag": ("y[2 * i + 1] = y[2 * i + 1] - pi;", "y[2 * i + 1] = y[2 * i + 1] + pi;"),
+    "complex_L_conjugated": ("z_mul(colk[2 * i], colk[2 * i + 1], xr, xi, &pr, &pi);",
+                             "z_mul(colk[2 * i], -colk[2 * i + 1], xr, xi, &pr, &pi);"),
+    "complex_alpha_conj": ("z_mul(alpha[0], alpha[1], y[2 * i], y[2 * i + 1], &r, &s);",
+                           "z_mul(alpha[0], -alpha[1], y[2 * i], y[2 * i + 1], &r, &s);"),
+    "rowform_index": ("for (int64_t k = 0; k < i; ++k) s = s - A[i + k * lda] * x[k];",
+                      "for (int64_t k = 0; k < i; ++k) s = s - A[k + i * lda] * x[k];"),
+    "residual_alpha_sign": ("dot2_add_prod(&acc, -alpha, B0[i + j * ldb]);",
+                            "dot2_add_prod(&acc, alpha, B0[i + j * ldb]);"),
+    "residual_dropped_diag": ("dot2_add_prod(&acc, unit ? 1.0 : A[i + i * lda], x[i]);", ""),
+    "norm_of_X_wrong": ("d_norm_inf_lower(unit, m, A, lda) * d_norm_inf_general(m, n, X, ldx)",
+                        "d_norm_inf_lower(unit, m, A, lda) * d_norm_inf_general(m, n, B0, ldb)"),
+}
+
+
+@pytest.mark.parametrize("name", sorted(MUTATIONS))
+def test_mutant_is_caught(tmp_path, name):
+    old, new = MUTATIONS[name]
+    src = oracle.source_text()
+    assert src.count(old) >= 1, f"mutation anchor for {name} not found"
+    mutated = src.replace(old, new, 1)
+    so = oracle.compile_variant(mutated, os.path.join(str(tmp_path), f"mut_{name}.so"))
+    orc = oracle.OracleLib(so)
+    failed = []
+    for pin in pins.ALL_PINS:
+        try:
+            pin(orc)
+        except (AssertionError, ValueError, FloatingPointError):
+            failed.append(pin.__name__)
+    assert failed, f"no pin catches the planted mistake {name}"
