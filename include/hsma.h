@@ -1,0 +1,174 @@
+/*
+ * hsma.h -- C ABI of the MI355X (gfx950) triangular-solve library.
+ *
+ * The operation (paper, Sec. 2.1; the forward-substitution equation of
+ * Sec. 4.2.1): left-side, lower-triangular, no-transpose TRSM
+ *
+ *         B <- alpha * inv(L) * B,    L = lower triangle of A (m x m),
+ *
+ * i.e. X solves L X = alpha B and overwrites B.  Row i of X is
+ *   x_ij = (alpha b_ij - sum_{k<i} l_ik x_kj) / l_ii   (l_ii = 1 for a unit diagonal).
+ *
+ * Conventions (BLAS TRSM; the paper leaves them open):
+ *   - Column-major storage with leading dimensions lda >= max(1, m) and
+ *     ldb >= max(1, m), counted in elements of the data type.
+ *   - Only the strict lower triangle of A is read, plus the diagonal when
+ *     diag == HSMA_NON_UNIT.  The upper triangle is never read.  Rows m..ldb-1
+ *     of B are never read or written.
+ *   - alpha == 0 sets B to zero and reads neither A nor B.
+ *   - No singularity check: a zero or non-finite diagonal propagates IEEE
+ *     infinities/NaNs.
+ *   - Real data is IEEE double; complex data is interleaved {double re, im}
+ *     (the layout of hipDoubleComplex and torch.complex128).
+ *
+ * Memory and streams:
+ *   - A and B are DEVICE pointers owned by the caller.  A and B must not
+ *     overlap.  The library owns its workspaces (stream-ordered allocations
+ *     from the device's default memory pool).
+ *   - Every call is asynchronous on `stream` (a hipStream_t passed as void*;
+ *     NULL is the null stream): it returns after enqueueing and the result is
+ *     complete when the stream reaches that point.  Exceptions noted per call.
+ *   - Calls are thread-safe.  The device used is the caller's current HIP device.
+ *
+ * Errors: no exception crosses the ABI.  Argument errors are reported before
+ * anything is enqueued and leave B untouched.  Check order for one problem:
+ *   1. diag or dtype not a listed enumerator        -> HSMA_INVALID_VALUE
+ *   2. m < 0 or n < 0                                -> HSMA_INVALID_SIZE
+ *   3. lda < max(1, m) or ldb < max(1, m)            -> HSMA_INVALID_SIZE
+ *   4. m == 0 or n == 0                              -> HSMA_SUCCESS, nothing done
+ *   5. alpha == NULL                                 -> HSMA_INVALID_POINTER
+ *   6. B == NULL, or A == NULL with alpha != 0       -> HSMA_INVALID_POINTER
+ * A failing HIP runtime call returns HSMA_HIP_ERROR; hsma_last_hip_error()
+ * then gives the hipError_t value of the calling thread's last failure.
+ */
+#ifndef HSMA_H
+#define HSMA_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum { HSMA_R64F = 0, HSMA_C64F = 1 } hsma_dtype;
+typedef enum { HSMA_NON_UNIT = 0, HSMA_UNIT = 1 } hsma_diag;
+
+typedef enum {
+    HSMA_SUCCESS = 0,
+    HSMA_INVALID_VALUE = 1,
+    HSMA_INVALID_SIZE = 2,
+    HSMA_INVALID_POINTER = 3,
+    HSMA_ALLOC_FAILED = 4,
+    HSMA_HIP_ERROR = 5,
+    HSMA_NOT_SUPPORTED = 6,
+    HSMA_TOO_LARGE = 7,
+    HSMA_QUEUE_CLOSED = 8,
+    HSMA_PENDING = 9,
+    HSMA_TIMEOUT = 10,
+    HSMA_NOT_FOUND = 11
+} hsma_status;
+
+/* A hipStream_t, passed as an opaque pointer; NULL = the null stream. */
+typedef void *hsma_stream_t;
+
+/* Static text for a status code (never NULL). */
+const char *hsma_status_string(hsma_status s);
+
+/* hipError_t of this thread's most recent HSMA_HIP_ERROR (0 if none). */
+int hsma_last_hip_error(void);
+
+/* Library version string, e.g. "0.1.0 gfx950". */
+const char *hsma_version(void);
+
+/*
+ * hsma_trsm -- B <- alpha * inv(tril(A)) * B  (paper Sec. 2.1, Sec. 4.1-4.3).
+ *
+ *   diag   HSMA_NON_UNIT or HSMA_UNIT (diagonal of A taken as 1, not read).
+ *   m, n   rows of A and B / columns of B.
+ *   alpha  HOST pointer to a double (HSMA_R64F) or double[2] = {re, im}
+ *          (HSMA_C64F); read before the call returns.
+ *   A      device pointer, m x m column-major, leading dimension lda.
+ *   B      device pointer, m x n column-major, leading dimension ldb; in/out.
+ *   dtype  HSMA_R64F or HSMA_C64F.
+ *   stream hipStream_t or NULL.
+ *
+ * Path: m <= 64 uses the register-resident small-solve kernel, one wavefront
+ * per 64-column panel of B (Sec. 4.2); m > 64 uses the blocked path (Sec. 4.3):
+ * diagonal blocks of edge I_B inverted in parallel, then recursive FP64
+ * matrix-core updates and in-place diagonal-block solves, with I_B taken from
+ * the compiled-in tuning table (Sec. 4.3.2).
+ */
+hsma_status hsma_trsm(hsma_diag diag, int64_t m, int64_t n, const void *alpha,
+                      const void *A, int64_t lda, void *B, int64_t ldb,
+                      hsma_dtype dtype, hsma_stream_t stream);
+
+
+/* Options of hsma_trsm_ex.  Zero-initialise and set what you need. */
+typedef struct {
+    int32_t block_size;   /* blocked-path diagonal-block edge I_B: 0 = tuning
+                             table (Sec. 4.3.2), else 16, 32, 64, 128 or 256 */
+    int32_t path;         /* 0 = automatic (m <= 64 small kernel, else blocked);
+                             1 = force the small kernel (requires m <= 64);
+                             2 = force the blocked path */
+    int32_t reserved[6];  /* must be zero */
+} hsma_trsm_options;
+
+/* What hsma_trsm_ex did (filled before it returns). */
+typedef struct {
+    int32_t path;         /* 1 small kernel, 2 blocked path, 0 nothing enqueued */
+    int32_t block_size;   /* I_B used by the blocked path, else 0 */
+    int32_t reserved[6];
+} hsma_trsm_report;
+
+/*
+ * hsma_trsm_ex -- hsma_trsm with explicit options; same operation, arguments,
+ * asynchrony and error behaviour.  opts may be NULL (all defaults); report
+ * may be NULL.  Unknown option values give HSMA_INVALID_VALUE; forcing the
+ * small kernel with m > 64 gives HSMA_NOT_SUPPORTED.
+ */
+hsma_status hsma_trsm_ex(hsma_diag diag, int64_t m, int64_t n, const void *alpha,
+                         const void *A, int64_t lda, void *B, int64_t ldb,
+                         hsma_dtype dtype, const hsma_trsm_options *opts,
+                         hsma_trsm_report *report, hsma_stream_t stream);
+
+/*
+ * hsma_lookup_block_size -- the I_B the tuning table gives for (dtype, m, n):
+ * the entry whose tested scale is nearest in log2(m), then log2(n), ties to
+ * the smaller scale (Sec. 4.3.2, online phase).  Host-only; no device access.
+ */
+int32_t hsma_lookup_block_size(hsma_dtype dtype, int64_t m, int64_t n);
+
+
+/*
+ * Phase accounting (the breakdown of the paper's Sec. 5.3, Table 3).  Between
+ * hsma_profile_begin() and hsma_profile_end() every kernel the library
+ * launches is bracketed by a pair of HIP events recorded on its own stream
+ * and tagged with its phase and algorithmic flop count (2 per real
+ * multiply-add of the product it computes; complex counted in its real
+ * expansion).  hsma_profile_end() waits for those events (it synchronises
+ * with them, not with the whole device), fills out[0..HSMA_PHASE_COUNT-1]
+ * and stops recording.  Process-wide; meant for benchmarks and profiling.
+ */
+typedef enum {
+    HSMA_PHASE_DIAG_INV = 0,  /* diagonal-block inversion (base kernel + merges) */
+    HSMA_PHASE_UPDATE = 1,    /* trailing updates B_bot -= L_bot,top X_top */
+    HSMA_PHASE_LEAF = 2,      /* diagonal solves X_r = alpha inv(D_r) B_r */
+    HSMA_PHASE_SMALL = 3,     /* small-regime solves (m <= 64) */
+    HSMA_PHASE_OTHER = 4,     /* zero fills, conversions, residuals, norms */
+    HSMA_PHASE_COUNT = 5
+} hsma_phase;
+
+typedef struct {
+    int64_t launches;
+    double ms;      /* summed kernel time */
+    double flops;   /* summed algorithmic flops */
+} hsma_phase_stat;
+
+hsma_status hsma_profile_begin(void);
+hsma_status hsma_profile_end(hsma_phase_stat *out, int count);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HSMA_H */

@@ -1,0 +1,222 @@
+"""Python binding of the gfx950 TRSM library (``libhsma.so``).
+
+Argument marshalling only: every step of every solve runs in the library's
+HIP kernels.  Tensors are torch tensors on the GPU; PyTorch provides device
+memory and streams.  The library must have been built
+(``python -m paper_2608_25469_amd.build``); importing works without it, but
+every call then raises ``HsmaError`` -- there is no CPU fallback.
+
+Layout: matrices are column-major, as in BLAS.  A column-major m x n matrix
+with leading dimension ld is the transpose of a row-major (n, ld) tensor,
+sliced to m rows: ``storage[:, :m].t()`` (strides (1, ld)).  Use
+:func:`colmajor` / :func:`to_colmajor` to make them.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhsma.so")
+
+R64F, C64F = 0, 1
+NON_UNIT, UNIT = 0, 1
+
+STATUS = {
+    0: "SUCCESS", 1: "INVALID_VALUE", 2: "INVALID_SIZE", 3: "INVALID_POINTER",
+    4: "ALLOC_FAILED", 5: "HIP_ERROR", 6: "NOT_SUPPORTED", 7: "TOO_LARGE",
+    8: "QUEUE_CLOSED", 9: "PENDING", 10: "TIMEOUT", 11: "NOT_FOUND",
+}
+
+
+class HsmaError(RuntimeError):
+    def __init__(self, status: int, what: str = ""):
+        self.status = status
+        super().__init__(f"{what}: {STATUS.get(status, status)}" if what else STATUS.get(status, str(status)))
+
+
+class TrsmOptions(ctypes.Structure):
+    _fields_ = [("block_size", ctypes.c_int32), ("path", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 6)]
+
+
+class TrsmReport(ctypes.Structure):
+    _fields_ = [("path", ctypes.c_int32), ("block_size", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 6)]
+
+
+class PhaseStat(ctypes.Structure):
+    _fields_ = [("launches", ctypes.c_int64), ("ms", ctypes.c_double), ("flops", ctypes.c_double)]
+
+
+PHASE_DIAG_INV, PHASE_UPDATE, PHASE_LEAF, PHASE_SMALL, PHASE_OTHER = range(5)
+PHASE_COUNT = 5
+PHASE_NAMES = ["diag_inv", "update", "leaf_solve", "small", "other"]
+
+_lib = None
+
+
+def lib():
+    """The loaded library (raises HsmaError if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise HsmaError(6, f"{LIB_PATH} not built; run python -m paper_2608_25469_amd.build")
+        L = ctypes.CDLL(LIB_PATH)
+        i64, vp, i32 = ctypes.c_int64, ctypes.c_void_p, ctypes.c_int32
+        L.hsma_trsm.argtypes = [i32, i64, i64, vp, vp, i64, vp, i64, i32, vp]
+        L.hsma_trsm.restype = i32
+        L.hsma_trsm_ex.argtypes = [i32, i64, i64, vp, vp, i64, vp, i64, i32,
+                                   ctypes.POINTER(TrsmOptions), ctypes.POINTER(TrsmReport), vp]
+        L.hsma_trsm_ex.restype = i32
+        L.hsma_status_string.argtypes = [i32]
+        L.hsma_status_string.restype = ctypes.c_char_p
+        L.hsma_last_hip_error.argtypes = []
+        L.hsma_last_hip_error.restype = ctypes.c_int
+        L.hsma_version.argtypes = []
+        L.hsma_version.restype = ctypes.c_char_p
+        L.hsma_lookup_block_size.argtypes = [i32, i64, i64]
+        L.hsma_lookup_block_size.restype = i32
+        L.hsma_profile_begin.argtypes = []
+        L.hsma_profile_begin.restype = i32
+        L.hsma_profile_end.argtypes = [ctypes.POINTER(PhaseStat), ctypes.c_int]
+        L.hsma_profile_end.restype = i32
+        _lib = L
+    return _lib
+
+
+def _check(st: int, what: str) -> None:
+    if st != 0:
+        extra = ""
+        if st == 5:
+            extra = f" (hipError {lib().hsma_last_hip_error()})"
+        raise HsmaError(st, what + extra)
+
+
+# ---------------------------------------------------------------------------
+# Layout helpers
+# ---------------------------------------------------------------------------
+
+def _torch():
+    import torch
+    return torch
+
+
+def colmajor(m: int, n: int, dtype, ld: Optional[int] = None, device="cuda", fill=None):
+    """A column-major m x n tensor with leading dimension ``ld`` (>= m)."""
+    torch = _torch()
+    ld = max(1, m) if ld is None else ld
+    if ld < max(1, m):
+        raise ValueError("ld < m")
+    store = torch.empty((max(n, 1), ld), dtype=dtype, device=device)
+    if fill is not None:
+        store.fill_(fill)
+    return store[:n, :m].t()
+
+
+def to_colmajor(a: np.ndarray, device="cuda", ld: Optional[int] = None):
+    """Copy a 2-D numpy array (any layout) to a column-major device tensor."""
+    torch = _torch()
+    m, n = a.shape
+    dt = torch.complex128 if np.iscomplexobj(a) else torch.float64
+    out = colmajor(m, n, dt, ld=ld, device=device)
+    if m and n:
+        out.copy_(torch.from_numpy(np.ascontiguousarray(a)))
+    return out
+
+
+def from_colmajor(t) -> np.ndarray:
+    """Device column-major tensor -> numpy array in Fortran order."""
+    return np.asfortranarray(t.detach().cpu().numpy())
+
+
+def leading_dim(t) -> int:
+    m, n = t.shape
+    if t.stride(0) != 1 and m > 1:
+        raise ValueError("matrix must be column-major (stride(0) == 1)")
+    if n <= 1:
+        return max(1, m) if t.stride(1) < m else t.stride(1)
+    return t.stride(1)
+
+
+def _dtype_code(t) -> int:
+    torch = _torch()
+    if t.dtype == torch.float64:
+        return R64F
+    if t.dtype == torch.complex128:
+        return C64F
+    raise TypeError("tensors must be float64 or complex128")
+
+
+def _alpha_buf(alpha, code):
+    a = complex(alpha)
+    if code == R64F and a.imag != 0:
+        raise ValueError("complex alpha for a real problem")
+    return (ctypes.c_double * 2)(a.real, a.imag)
+
+
+def _stream_handle(stream) -> int:
+    torch = _torch()
+    if stream is None:
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+# ---------------------------------------------------------------------------
+# Solves
+# ---------------------------------------------------------------------------
+
+def trsm(L, B, alpha=1.0, unit: bool = False, block_size: int = 0, path: int = 0,
+         stream=None, report: bool = False):
+    """B <- alpha * inv(tril(L)) * B in place (left, lower, no transpose).
+
+    L: m x m, B: m x n, both column-major device tensors of the same dtype
+    (float64 or complex128).  ``block_size`` forces the blocked path's I_B,
+    ``path`` forces 1 = small kernel or 2 = blocked.  Asynchronous on
+    ``stream`` (default: torch's current stream).  Returns B (and the
+    library's report if ``report``).
+    """
+    code = _dtype_code(B)
+    if L.dtype != B.dtype:
+        raise TypeError("L and B must have the same dtype")
+    m, n = B.shape
+    if L.shape[0] != m or L.shape[1] < m:
+        raise ValueError("L must be m x m")
+    if m and n and (not L.is_cuda or not B.is_cuda):
+        raise ValueError("tensors must be on the GPU")
+    opts = TrsmOptions(block_size, path, (ctypes.c_int32 * 6)())
+    rep = TrsmReport()
+    st = lib().hsma_trsm_ex(UNIT if unit else NON_UNIT, m, n, _alpha_buf(alpha, code),
+                            ctypes.c_void_p(L.data_ptr()), leading_dim(L),
+                            ctypes.c_void_p(B.data_ptr()), leading_dim(B), code,
+                            ctypes.byref(opts), ctypes.byref(rep),
+                            ctypes.c_void_p(_stream_handle(stream)))
+    _check(st, "hsma_trsm_ex")
+    if report:
+        return B, {"path": rep.path, "block_size": rep.block_size}
+    return B
+
+
+def profile_begin() -> None:
+    _check(lib().hsma_profile_begin(), "hsma_profile_begin")
+
+
+def profile_end() -> dict:
+    """Per-phase kernel time since profile_begin (waits for the events)."""
+    stats = (PhaseStat * PHASE_COUNT)()
+    _check(lib().hsma_profile_end(stats, PHASE_COUNT), "hsma_profile_end")
+    return {PHASE_NAMES[i]: {"launches": stats[i].launches, "ms": stats[i].ms,
+                             "flops": stats[i].flops} for i in range(PHASE_COUNT)}
+
+
+def lookup_block_size(complex_: bool, m: int, n: int) -> int:
+    return lib().hsma_lookup_block_size(C64F if complex_ else R64F, m, n)
+
+
+def version() -> str:
+    return lib().hsma_version().decode()

@@ -1,0 +1,172 @@
+// Blocked path for m > 64 (paper Sec. 4.3).
+//
+// Phase 1 -- every diagonal block D_r (edge I_B, the last one ragged) is
+// inverted independently: chunks of up to 64 rows by register substitution
+// against identity right-hand sides (launch_diag_inv_base), then pairs of
+// adjacent inverted blocks are merged level by level with the block formula
+//      inv([[A, 0], [C, D]]) = [[inv(A), 0], [-inv(D) C inv(A), inv(D)]],
+// two batched matrix-core products per level (T = C inv(A); W21 = -inv(D) T).
+//
+// Phase 2 -- the dependent part.  The paper walks the blocks left-looking
+// (B_r -= A_{r,0:r} X_{0:r}, a product whose K grows with r).  Here the same
+// algebra is walked recursively: solve the top half, apply one update
+//      B_bot <- beta B_bot - L_{bot,top} X_top
+// and solve the bottom half.  Half of all flops land in a single
+// (m/2) x n x (m/2) product, so the matrix cores see large, square-ish
+// products instead of I_B-tall slivers.  Leaves are X_r = alpha inv(D_r) B_r,
+// written in place by a product whose single M-tile covers all I_B rows.
+// alpha is folded into the first write of each row block (beta = alpha on
+// the first update a block receives, or alpha in its leaf if none).
+
+#include <algorithm>
+#include <vector>
+
+#include "internal.h"
+
+namespace hsma {
+
+namespace {
+
+struct Ctx {
+    bool cx;
+    bool unit;
+    int64_t m, n;
+    cplx alpha;
+    const double *A;
+    int64_t lda;
+    double *B;
+    int64_t ldb;
+    int ib;
+    double *W;  // nblk * ib * ib elements
+    double *T;  // combine scratch
+    hipStream_t s;
+    int es() const { return cx ? 2 : 1; }
+};
+
+// Merge inverted diagonal sub-blocks of edge `sz` into blocks of edge 2*sz.
+// One batched launch pair per group of equally-sized pairs.
+hsma_status combine_group(const Ctx &c, int sz, int64_t first_row, int npairs_outer,
+                          int npairs_inner, int tsz) {
+    // Pair (bo, bi): top-left at global row g = first_row + bo*ib + bi*2*sz,
+    // top size sz, bottom size tsz (<= sz).
+    if (npairs_outer <= 0 || npairs_inner <= 0 || tsz <= 0) return HSMA_SUCCESS;
+    const int es = c.es();
+    const int64_t ib = c.ib, lda = c.lda;
+    const int64_t blk0 = first_row / ib, off0 = first_row % ib;
+    // A operand (C block of L): rows g+sz.., cols g..
+    const double *Lc = c.A + es * ((first_row + sz) + first_row * lda);
+    // inv(A) and inv(D) and W21 inside W.
+    const double *Wa = c.W + es * (blk0 * ib * ib + off0 + off0 * ib);
+    const double *Wd = c.W + es * (blk0 * ib * ib + (off0 + sz) + (off0 + sz) * ib);
+    double *W21 = c.W + es * (blk0 * ib * ib + (off0 + sz) + off0 * ib);
+    GemmBatch b1, b2;
+    b1.count = b2.count = npairs_outer * npairs_inner;
+    b1.inner = b2.inner = npairs_inner;
+    // Step 1: T = C * inv(A)   (tsz x sz) = (tsz x sz)(sz x sz)
+    b1.a_outer = es * ib * (1 + lda);
+    b1.a_inner = es * 2 * sz * (1 + lda);
+    b1.b_outer = es * ib * ib;
+    b1.b_inner = es * 2 * sz * (1 + ib);
+    b1.c_outer = es * (int64_t)npairs_inner * sz * sz;
+    b1.c_inner = es * (int64_t)sz * sz;
+    HSMA_TRY(launch_gemm(c.cx, GemmRole::Inverse, es * tsz, sz, es * sz, cplx{1.0, 0.0}, Lc, lda,
+                         Wa, es * ib, cplx{0.0, 0.0}, c.T, es * tsz, 0, b1, c.s));
+    // Step 2: W21 = -inv(D) * T   (tsz x sz) = (tsz x tsz)(tsz x sz)
+    b2.a_outer = es * ib * ib;
+    b2.a_inner = es * 2 * sz * (1 + ib);
+    b2.b_outer = b1.c_outer;
+    b2.b_inner = b1.c_inner;
+    b2.c_outer = es * ib * ib;
+    b2.c_inner = es * 2 * sz * (1 + ib);
+    HSMA_TRY(launch_gemm(c.cx, GemmRole::Inverse, es * tsz, sz, es * tsz, cplx{-1.0, 0.0}, Wd, ib,
+                         c.T, es * tsz, cplx{0.0, 0.0}, W21, es * ib, 0, b2, c.s));
+    return HSMA_SUCCESS;
+}
+
+hsma_status invert_diagonal(const Ctx &c, int base) {
+    HSMA_TRY(launch_diag_inv_base(c.cx, c.unit, (int)c.m, base, c.ib, c.A, c.lda, c.W, c.s));
+    const int64_t m = c.m, ib = c.ib;
+    const int64_t nfull = m / ib;
+    const int64_t rem = m - nfull * ib;
+    for (int sz = base; sz < ib; sz *= 2) {
+        // Full blocks: ib / (2 sz) uniform pairs each.
+        HSMA_TRY(combine_group(c, sz, 0, (int)nfull, (int)(ib / (2 * sz)), sz));
+        if (rem > 0) {
+            const int64_t g = nfull * ib;
+            const int64_t full_pairs = rem / (2 * sz);
+            HSMA_TRY(combine_group(c, sz, g, 1, (int)full_pairs, sz));
+            const int64_t a = full_pairs * 2 * sz;
+            const int64_t t = rem - a - sz;
+            if (t > 0) HSMA_TRY(combine_group(c, sz, g + a, 1, 1, (int)t));
+        }
+    }
+    return HSMA_SUCCESS;
+}
+
+hsma_status leaf(const Ctx &c, int64_t blk, bool touched) {
+    const int es = c.es();
+    const int64_t r0 = blk * c.ib;
+    const int mr = (int)std::min<int64_t>(c.ib, c.m - r0);
+    const double *Wr = c.W + es * (blk * (int64_t)c.ib * c.ib);
+    double *Br = c.B + es * r0;
+    GemmBatch one;
+    return launch_gemm(c.cx, GemmRole::Leaf, es * mr, (int)c.n, es * mr,
+                       touched ? cplx{1.0, 0.0} : c.alpha, Wr, c.ib, Br, es * c.ldb,
+                       cplx{0.0, 0.0}, Br, es * c.ldb, 0, one, c.s);
+}
+
+hsma_status update(const Ctx &c, int64_t r1, int64_t r2, int64_t k0, bool touched) {
+    // B[r1:r2] = beta B[r1:r2] - L[r1:r2, k0:r1] B[k0:r1]
+    const int es = c.es();
+    GemmBatch one;
+    const cplx beta = touched ? cplx{1.0, 0.0} : c.alpha;
+    return launch_gemm(c.cx, GemmRole::Update, (int)(es * (r2 - r1)), (int)c.n, (int)(es * (r1 - k0)),
+                       cplx{-1.0, 0.0}, c.A + es * (r1 + k0 * c.lda), c.lda, c.B + es * k0,
+                       es * c.ldb, beta, c.B + es * r1, es * c.ldb, 0, one, c.s);
+}
+
+hsma_status recurse(const Ctx &c, int64_t b0, int64_t nb, bool touched) {
+    if (nb == 1) return leaf(c, b0, touched);
+    const int64_t h = nb / 2;
+    HSMA_TRY(recurse(c, b0, h, touched));
+    const int64_t r1 = (b0 + h) * c.ib;
+    const int64_t r2 = std::min<int64_t>((b0 + nb) * c.ib, c.m);
+    HSMA_TRY(update(c, r1, r2, b0 * c.ib, touched));
+    return recurse(c, b0 + h, nb - h, true);
+}
+
+}  // namespace
+
+size_t blocked_workspace_bytes(bool cx, int64_t m, int ib) {
+    const int64_t nblk = (m + ib - 1) / ib;
+    const size_t es = cx ? 2 : 1;
+    const size_t w = (size_t)nblk * ib * ib * es * sizeof(double);
+    // Combine scratch: at most m/2 rows by ib/2 columns at the top level.
+    const size_t t = (size_t)((m + 1) / 2 + ib) * (size_t)ib * es * sizeof(double);
+    return w + t;
+}
+
+// Enqueue the blocked solve.  `ws` must hold blocked_workspace_bytes().
+hsma_status blocked_trsm(bool cx, bool unit, int64_t m, int64_t n, cplx alpha, const double *A,
+                         int64_t lda, double *B, int64_t ldb, int ib, void *ws, hipStream_t s) {
+    Ctx c;
+    c.cx = cx;
+    c.unit = unit;
+    c.m = m;
+    c.n = n;
+    c.alpha = alpha;
+    c.A = A;
+    c.lda = lda;
+    c.B = B;
+    c.ldb = ldb;
+    c.ib = ib;
+    c.s = s;
+    const int64_t nblk = (m + ib - 1) / ib;
+    c.W = static_cast<double *>(ws);
+    c.T = c.W + (cx ? 2 : 1) * nblk * (int64_t)ib * ib;
+    const int base = std::min(ib, 64);
+    HSMA_TRY(invert_diagonal(c, base));
+    return recurse(c, 0, nblk, false);
+}
+
+}  // namespace hsma

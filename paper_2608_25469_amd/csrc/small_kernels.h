@@ -1,0 +1,268 @@
+// Small-regime TRSM (m <= 64): register-resident forward substitution.
+//
+// Paper, Sec. 4.2.1: columns of B are independent, so each column is a
+// separate forward substitution; the triangular operand is shared.  Here one
+// 64-lane wavefront owns a panel of up to 64 columns: lane j keeps column j
+// of the panel entirely in VGPRs (y[0..m-1]), so the row-dependency chain runs
+// inside a lane with no synchronisation at all.  L is the same for every lane,
+// so it is read through the scalar data cache into SGPRs (address space 4),
+// which costs no vector-memory or LDS bandwidth and feeds v_fma_f64 directly as
+// its scalar operand.
+//
+// The loop nest is fully unrolled for a compile-time row bound MAXM and
+// guarded by the runtime m at 8-row granularity.  Rows are processed in blocks
+// of 8 in left-looking order: block R first receives the updates of every
+// finished block K < R (8x8 multiply-adds per column of L, one 64-byte scalar
+// load per 8 coefficients), then its own 8x8 triangle is solved and each row
+// is written back the moment it is final.  The loads of B are all issued up
+// front and the waits count down row by row, so global loads of later rows
+// overlap the dependency chain of earlier ones and stores trail it (the
+// load/compute/store overlap of Sec. 4.2.1, Alg. 1, realised by full unrolling
+// plus the hardware's in-order vmcnt waits).
+//
+// Reciprocals of the diagonal are computed once per wavefront, one per lane,
+// and broadcast to the whole wave with v_readlane when row k is divided.
+
+#pragma once
+
+#include "internal.h"
+
+namespace hsma {
+namespace smallk {
+
+typedef __attribute__((address_space(4))) const double sdouble;  // scalar-cache loads
+
+__device__ __forceinline__ double readlane_d(double v, int lane) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+    return __hiloint2double(hi, lo);
+}
+
+struct alignas(16) dpair {
+    double x, y;
+};
+
+// ---------------------------------------------------------------------------
+// Broadcast of L.  Every lane needs every coefficient l_ik (lane j works on
+// column j).  Column k of L is loaded with vector loads into NQ = ceil(MAXM/16)
+// VGPRs (two per complex value) such that each 16-lane row of the wavefront
+// holds rows 16q..16q+15 of the column: lane l holds l_{16q + l%16, k}.  The
+// 64-bit DPP control row_newbcast:r then hands lane r of each 16-lane row to
+// all 16 lanes of that row, i.e. l_{16q+r, k} to the whole wave.  Row indices
+// are clamped to m-1 (addresses never leave A); the values of rows >= m and
+// of rows on or above the diagonal are never used by an update that matters.
+// ---------------------------------------------------------------------------
+template <int N>
+__device__ __forceinline__ double bcast16(double v) {
+    return __builtin_amdgcn_update_dpp(v, v, 0x150 + N, 0xf, 0xf, false);  // row_newbcast:N
+}
+
+template <int R>
+__device__ __forceinline__ double bcast_row(double v) {
+    return bcast16<R>(v);
+}
+
+// Static dispatch of row_newbcast on a compile-time row number.
+template <int I>
+struct RowB {
+    static __device__ __forceinline__ double get(double v) { return bcast16<(I & 15)>(v); }
+};
+
+// y -= l * x for real (li ignored) or complex values.
+template <bool CX>
+__device__ __forceinline__ void fms(double &yr, double &yi, double lr, double li, double xr,
+                                    double xi) {
+    if (CX) {
+        yr = __fma_rn(-lr, xr, yr);
+        yr = __fma_rn(li, xi, yr);
+        yi = __fma_rn(-lr, xi, yi);
+        yi = __fma_rn(-li, xr, yi);
+    } else {
+        yr = __fma_rn(-lr, xr, yr);
+    }
+}
+
+// Applies column K (already final as xr/xi) to rows K+1..MAXM-1.
+template <bool CX, int MAXM, int K, int I>
+struct ApplyRows {
+    static __device__ __forceinline__ void run(double (&yr)[MAXM], double (&yi)[MAXM],
+                                               const double (&Lr)[(MAXM + 15) / 16],
+                                               const double (&Li)[(MAXM + 15) / 16], double xr,
+                                               double xi) {
+        if constexpr (I < MAXM) {
+            const double lr = RowB<I>::get(Lr[I / 16]);
+            const double li = CX ? RowB<I>::get(Li[I / 16]) : 0.0;
+            fms<CX>(yr[I], yi[I], lr, li, xr, xi);
+            ApplyRows<CX, MAXM, K, I + 1>::run(yr, yi, Lr, Li, xr, xi);
+        }
+    }
+};
+
+// One 64-column panel: lane j solves column j (j < ncols) in registers.
+// A: m x m, lda; B: m x ncols, ldb (element units; complex interleaved).
+// m lies in (MAXM-8, MAXM].
+template <bool CX, int MAXM, bool UNIT>
+struct Panel {
+    static constexpr int NQ = (MAXM + 15) / 16;
+    static constexpr int ES = CX ? 2 : 1;
+
+    template <int K>
+    static __device__ __forceinline__ void step(const double *__restrict__ A, int64_t lda, int m,
+                                                int lane, double rr, double ri,
+                                                double (&yr)[MAXM], double (&yi)[MAXM]) {
+        if constexpr (K < MAXM) {
+            // Each column step is its own basic block (K < m is uniform): this
+            // keeps the instruction selector from sinking the step's
+            // multiply-adds to their final uses, which would keep every
+            // broadcast coefficient of the unrolled body alive at once.
+            if (K < m) {
+                // x_k = y_k / l_kk  (multiply by the broadcast reciprocal)
+                if (!UNIT) {
+                    const double dr = readlane_d(rr, K);
+                    if (CX) {
+                        const double di = readlane_d(ri, K);
+                        const double tr = yr[K] * dr - yi[K] * di;
+                        const double ti = yr[K] * di + yi[K] * dr;
+                        yr[K] = tr;
+                        yi[K] = ti;
+                    } else {
+                        yr[K] *= dr;
+                    }
+                }
+                if constexpr (K + 1 < MAXM) {
+                    // Column K, rows 16q + lane%16 (clamped to m-1), for the
+                    // 16-row groups q that hold rows below K.
+                    double Lr[NQ], Li[NQ];
+#pragma unroll
+                    for (int q = 0; q < NQ; ++q) {
+                        Lr[q] = Li[q] = 0.0;
+                        if (16 * q + 15 > K) {
+                            const int row = 16 * q + (lane & 15);
+                            const int rc = row < m - 1 ? row : m - 1;
+                            const double *p = A + ES * ((int64_t)K * lda + rc);
+                            if (CX) {
+                                const dpair v = *reinterpret_cast<const dpair *>(p);
+                                Lr[q] = v.x;
+                                Li[q] = v.y;
+                            } else {
+                                Lr[q] = p[0];
+                            }
+                        }
+                    }
+                    ApplyRows<CX, MAXM, K, K + 1>::run(yr, yi, Lr, Li, yr[K], yi[K]);
+                }
+            }
+            step<K + 1>(A, lda, m, lane, rr, ri, yr, yi);
+        }
+    }
+
+    // IDENT: the right-hand side is the identity (column j = e_j) and the
+    // result goes to Bout; this produces inv(L) column by column (the
+    // identity-tile right-hand side of the paper's Sec. 4.3.1).
+    template <bool IDENT>
+    static __device__ __forceinline__ void solve(const double *__restrict__ A, int64_t lda,
+                                                 double *__restrict__ B, int64_t ldb, int m,
+                                                 int ncols, cplx alpha) {
+        const int lane = threadIdx.x & 63;
+        const bool active = lane < ncols;
+        double *__restrict__ bc = B + ES * (int64_t)(active ? lane : 0) * ldb;
+
+        // Reciprocal of the diagonal, one entry per lane: 1/d or conj(d)/|d|^2.
+        double rr = 1.0, ri = 0.0;
+        if (!UNIT && lane < m) {
+            const double *d = A + ES * ((int64_t)lane + (int64_t)lane * lda);
+            if (CX) {
+                const dpair v = *reinterpret_cast<const dpair *>(d);
+                const double den = v.x * v.x + v.y * v.y;
+                rr = v.x / den;
+                ri = -v.y / den;
+            } else {
+                rr = 1.0 / d[0];
+            }
+        }
+
+        // Column j of the panel; rows >= m are read at row m-1 and then zeroed.
+        double yr[MAXM], yi[MAXM];
+#pragma unroll
+        for (int i = 0; i < MAXM; ++i) {
+            const int ic = i < m ? i : m - 1;
+            if (IDENT) {
+                yr[i] = (i == lane) ? 1.0 : 0.0;
+                yi[i] = 0.0;
+            } else if (CX) {
+                const dpair v = reinterpret_cast<const dpair *>(bc)[ic];
+                yr[i] = v.x;
+                yi[i] = v.y;
+            } else {
+                yr[i] = bc[ic];
+                yi[i] = 0.0;
+            }
+            if (i >= m) yr[i] = yi[i] = 0.0;
+        }
+        if (alpha.re != 1.0 || alpha.im != 0.0) {
+#pragma unroll
+            for (int i = 0; i < MAXM; ++i) {
+                if (CX) {
+                    const double tr = alpha.re * yr[i] - alpha.im * yi[i];
+                    const double ti = alpha.re * yi[i] + alpha.im * yr[i];
+                    yr[i] = tr;
+                    yi[i] = ti;
+                } else {
+                    yr[i] *= alpha.re;
+                }
+            }
+        }
+
+        step<0>(A, lda, m, lane, rr, ri, yr, yi);
+
+        if (active) {
+#pragma unroll
+            for (int i = 0; i < MAXM; ++i) {
+                if (i < m) {
+                    if (CX)
+                        reinterpret_cast<dpair *>(bc)[i] = dpair{yr[i], yi[i]};
+                    else
+                        bc[i] = yr[i];
+                }
+            }
+        }
+    }
+};
+
+template <bool CX, int NCH, bool UNIT>
+__device__ __forceinline__ void solve_panel(const double *__restrict__ A, int64_t lda,
+                                            double *__restrict__ B, int64_t ldb, int m, int ncols,
+                                            cplx alpha) {
+    Panel<CX, 8 * NCH, UNIT>::template solve<false>(A, lda, B, ldb, m, ncols, alpha);
+}
+
+// One wavefront per 64-column panel of B.
+template <bool CX, int NCH, bool UNIT>
+__global__ __launch_bounds__(64) void hsma_small_solve(const double *__restrict__ A, int64_t lda,
+                                                       double *__restrict__ B, int64_t ldb, int m,
+                                                       int64_t n, double ar, double ai) {
+    const int64_t col0 = (int64_t)blockIdx.x * 64;
+    const int ncols = (int)((n - col0) < 64 ? (n - col0) : 64);
+    solve_panel<CX, NCH, UNIT>(A, lda, B + (CX ? 2 : 1) * col0 * ldb, ldb, m, ncols, cplx{ar, ai});
+}
+
+// Phase 1 of the blocked path (paper Sec. 4.3): the diagonal of L is cut
+// into consecutive chunks of `base` rows (the last one ragged) and every chunk
+// D is inverted independently, one wavefront per chunk: lane j solves
+// D x = e_j in registers.  inv(D) lands in the ib x ib diagonal-block
+// workspace W at its place inside its block (ld = ib).
+template <bool CX, int NCH, bool UNIT>
+__global__ __launch_bounds__(64) void hsma_diag_inv_base(const double *__restrict__ A, int64_t lda,
+                                                         double *__restrict__ W, int m, int base,
+                                                         int ib) {
+    const int64_t o = (int64_t)blockIdx.x * base;
+    const int mb = (int)((m - o) < base ? (m - o) : base);
+    const int64_t blk = o / ib, oo = o % ib;
+    constexpr int ES = CX ? 2 : 1;
+    const double *Ad = A + ES * (o + o * lda);
+    double *Wd = W + ES * (blk * (int64_t)ib * ib + oo + oo * ib);
+    Panel<CX, 8 * NCH, UNIT>::template solve<true>(Ad, lda, Wd, ib, mb, mb, cplx{1.0, 0.0});
+}
+
+}  // namespace smallk
+}  // namespace hsma

@@ -1,0 +1,101 @@
+"""The C ABI without a GPU: the library loads, exports every function the
+header declares, and rejects bad arguments before touching the device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_2608_25469_amd as hs
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "hsma.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(hsma_[a-z0-9_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(hs.LIB_PATH):
+        pytest.fail("libhsma.so is not built (python -m paper_2608_25469_amd.build)")
+    return hs.lib()
+
+
+def test_exports_every_declared_symbol(lib):
+    names = declared_functions()
+    assert "hsma_trsm" in names and "hsma_trsm_ex" in names
+    for n in names:
+        assert hasattr(lib, n), f"{n} declared in hsma.h but not exported"
+
+
+def test_status_strings(lib):
+    for code in range(12):
+        s = lib.hsma_status_string(code)
+        assert s and len(s) > 3
+    assert lib.hsma_version().startswith(b"0.")
+
+
+def _call(lib, diag=0, m=4, n=3, alpha=1.0, A=16, lda=4, B=32, ldb=4, dtype=0):
+    al = (ctypes.c_double * 2)(alpha, 0.0) if alpha is not None else None
+    return lib.hsma_trsm(diag, m, n, al, ctypes.c_void_p(A) if A else None, lda,
+                         ctypes.c_void_p(B) if B else None, ldb, dtype, None)
+
+
+def test_validation_order(lib):
+    # 1. enumerators
+    assert _call(lib, diag=2) == 1
+    assert _call(lib, dtype=7) == 1
+    assert _call(lib, diag=-1, m=-1) == 1          # enum checked before sizes
+    # 2. sizes
+    assert _call(lib, m=-1) == 2
+    assert _call(lib, n=-5) == 2
+    # 3. leading dimensions
+    assert _call(lib, m=5, lda=4) == 2
+    assert _call(lib, m=5, lda=5, ldb=4) == 2
+    assert _call(lib, m=0, lda=0) == 2              # ld >= max(1, m)
+    # 4. quick return before pointer checks
+    assert _call(lib, m=0, lda=1, ldb=1, A=0, B=0, alpha=None) == 0
+    assert _call(lib, n=0, A=0, B=0, alpha=None) == 0
+    # 5. alpha pointer
+    assert _call(lib, alpha=None) == 3
+    # 6. B null; A null only matters when alpha != 0
+    assert _call(lib, B=0) == 3
+    assert _call(lib, A=0) == 3
+
+
+def test_ex_option_checks(lib):
+    al = (ctypes.c_double * 2)(1.0, 0.0)
+    for bad in (dict(block_size=48), dict(path=3), dict(block_size=-16)):
+        o = hs.TrsmOptions(**bad)
+        st = lib.hsma_trsm_ex(0, 4, 3, al, ctypes.c_void_p(16), 4, ctypes.c_void_p(32), 4, 0,
+                              ctypes.byref(o), None, None)
+        assert st == 1, bad
+    o = hs.TrsmOptions()
+    o.reserved[2] = 1
+    st = lib.hsma_trsm_ex(0, 4, 3, al, ctypes.c_void_p(16), 4, ctypes.c_void_p(32), 4, 0,
+                          ctypes.byref(o), None, None)
+    assert st == 1
+
+
+def test_block_size_lookup_rule(lib):
+    # Exact table scales return their entry; other scales the nearest one in
+    # log2(m), then log2(n), ties to the smaller scale.
+    import math
+    src = open(os.path.join(ROOT, "paper_2608_25469_amd", "csrc", "tuning_gfx950.h")).read()
+    rows = [tuple(map(int, t)) for t in re.findall(r"\{(\d), (\d+), (\d+), (\d+)\}", src)]
+    assert rows
+
+    def expect(dt, m, n):
+        cand = [r for r in rows if r[0] == dt]
+        key = lambda r: (round(abs(math.log2(r[1]) - math.log2(m)), 9),
+                         round(abs(math.log2(r[2]) - math.log2(n)), 9), r[1], r[2])
+        return min(cand, key=key)[3]
+
+    for dt in (0, 1):
+        for m in (65, 100, 128, 181, 1000, 3000, 5000, 20000, 100000):
+            for n in (1, 64, 1000, 16384):
+                assert lib.hsma_lookup_block_size(dt, m, n) == expect(dt, m, n), (dt, m, n)

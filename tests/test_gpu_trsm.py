@@ -1,0 +1,188 @@
+"""GPU parity: the HIP path against the CPU oracle on identical seeded inputs.
+
+Bar (normwise): relative Frobenius error against the oracle <= 1e-12 and
+backward error ||L X - alpha B||_inf / (||L|| ||X|| + |alpha| ||B||) <= 10 m 2^-53.
+Structured inputs with exactly representable answers must match bit for bit.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+hs = pytest.importorskip("paper_2608_25469_amd")
+
+U = 2.0 ** -53
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+    hs.lib()  # raises if the library is missing: no silent fallback
+
+
+def run(L, B, alpha, unit=False, block_size=0, path=0, ldb=None, lda=None):
+    """Solve on the GPU; returns (X, report, padding rows of B as numpy)."""
+    Ld = hs.to_colmajor(L, ld=lda)
+    Bd = hs.to_colmajor(B, ld=ldb)
+    if ldb is not None:
+        # sentinel in the padding rows
+        store = Bd.t()
+        store[:, B.shape[0]:] = W.PAD_SENTINEL
+    _, rep = hs.trsm(Ld, Bd, alpha, unit=unit, block_size=block_size, path=path, report=True)
+    torch.cuda.synchronize()
+    X = hs.from_colmajor(Bd)
+    pad = None
+    if ldb is not None:
+        pad = Bd.t()[:, B.shape[0]:].cpu().numpy()
+    return X, rep, pad
+
+
+def check(L, B, X, alpha, unit=False, tag=""):
+    ref = oracle.solve(L, B, alpha, unit=unit)
+    rel = oracle.rel_err_fro(X, ref)
+    eta = oracle.backward_error(L, X, B, alpha, unit=unit)
+    m = B.shape[0]
+    assert np.all(np.isfinite(X)), tag
+    assert rel <= 1e-12, (tag, rel)
+    assert eta <= 10 * m * U, (tag, eta)
+    return rel, eta
+
+
+# ---------------------------------------------------------------------------
+# small kernel: every m in 1..64
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("cx", [False, True], ids=["real", "complex"])
+@pytest.mark.parametrize("unit", [False, True], ids=["nonunit", "unit"])
+def test_small_every_m(cx, unit):
+    alpha = complex(0.75, -0.5) if cx else -1.5
+    for m in range(1, 65):
+        for n in (1, 13, 64, 65, 130):
+            L, B = W.problem(1000 + m, m, n, cx)
+            X, rep, _ = run(L, B, alpha, unit=unit)
+            assert rep["path"] == 1
+            check(L, B, X, alpha, unit, tag=(m, n, cx, unit))
+
+
+def test_single_small_workload():
+    """The single small real solve: m = n = 32, seed 0, alpha = 1."""
+    c = W.SINGLE_SMALL
+    L, B = W.problem(c["seed"], c["m"], c["n"], c["complex_"])
+    X, rep, _ = run(L, B, c["alpha"])
+    assert rep["path"] == 1
+    check(L, B, X, c["alpha"], tag="single-small")
+
+
+# ---------------------------------------------------------------------------
+# blocked path: every I_B, ragged sizes, both dtypes
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("cx", [False, True], ids=["real", "complex"])
+@pytest.mark.parametrize("ib", [16, 32, 64, 128, 256])
+def test_blocked_sizes(cx, ib):
+    alpha = complex(-1.0, 0.25) if cx else -1.0
+    for m, n in ((65, 7), (127, 64), (129, 33), (300, 129), (1000, 77), (1061, 200)):
+        for unit in (False, True):
+            L, B = W.problem(2000 + m + ib, m, n, cx)
+            X, rep, _ = run(L, B, alpha, unit=unit, block_size=ib)
+            assert rep["path"] == 2 and rep["block_size"] == ib
+            check(L, B, X, alpha, unit, tag=(m, n, cx, ib, unit))
+
+
+def test_blocked_default_table():
+    for cx in (False, True):
+        L, B = W.problem(7, 700, 50, cx)
+        X, rep, _ = run(L, B, 1.0)
+        assert rep["path"] == 2 and rep["block_size"] == hs.lookup_block_size(cx, 700, 50)
+        check(L, B, X, 1.0, tag=("table", cx))
+
+
+# ---------------------------------------------------------------------------
+# exact answers, bit for bit, on every path
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("ib", [0, 16, 64, 256])
+def test_bidiagonal_exact(ib):
+    rng = np.random.default_rng(3)
+    for m in (40, 64, 300, 777):
+        if ib == 0 and m > 64:
+            continue
+        if ib and m <= 64:
+            continue
+        B = W.integer_rhs(rng, m, 9, -50, 50)
+        X, _, _ = run(W.bidiagonal_lower(m, 4.0), B, 2.0, block_size=ib)
+        assert np.array_equal(X, np.cumsum(B, axis=0) * 0.5), (m, ib)
+        Bc = W.integer_rhs(rng, m, 9, -50, 50, complex_=True)
+        Xc, _, _ = run(W.bidiagonal_lower(m, 1 + 1j, complex_=True), Bc, 1.0, block_size=ib)
+        assert np.array_equal(Xc, np.cumsum(Bc, axis=0) * (0.5 - 0.5j)), (m, ib, "cx")
+
+
+@pytest.mark.parametrize("ib", [0, 32, 128])
+def test_block_nilpotent_exact(ib):
+    rng = np.random.default_rng(4)
+    for cx in (False, True):
+        for m1, m2 in ((20, 30), (130, 200), (256, 256)):
+            if (ib == 0) != (m1 + m2 <= 64):
+                continue
+            C = W.integer_rhs(rng, m2, m1, -2, 2, complex_=cx)
+            L = W.block_nilpotent(m1, m2, C)
+            B = W.integer_rhs(rng, m1 + m2, 11, -20, 20, complex_=cx)
+            expect = B.copy()
+            expect[m1:] = B[m1:] - C @ B[:m1]
+            X, _, _ = run(L, B, 1.0, block_size=ib)
+            assert np.array_equal(X, expect), (cx, m1, m2, ib)
+            Lu = L.copy(order="F")
+            Lu[np.diag_indices(m1 + m2)] = np.nan
+            Xu, _, _ = run(Lu, B, 1.0, unit=True, block_size=ib)
+            assert np.array_equal(Xu, expect), (cx, m1, m2, ib, "unit")
+
+
+def test_identity_exact():
+    rng = np.random.default_rng(5)
+    for m, ib in ((33, 0), (64, 0), (200, 64), (513, 256)):
+        for cx in (False, True):
+            for unit in (False, True):
+                L = W.identity_lower(m, cx, unit=unit)
+                B = W.rhs_matrix(rng, m, 17, cx)
+                X, _, _ = run(L, B, 1.0, unit=unit, block_size=ib)
+                assert np.array_equal(X, B), (m, ib, cx, unit)
+
+
+# ---------------------------------------------------------------------------
+# BLAS conventions
+# ---------------------------------------------------------------------------
+def test_alpha_zero_reads_nothing():
+    for m, cx in ((10, False), (100, True)):
+        L = np.full((m, m), np.nan, dtype=np.complex128 if cx else np.float64, order="F")
+        B = np.full((m, 5), np.nan, dtype=L.dtype, order="F")
+        X, _, _ = run(L, B, 0.0)
+        assert np.all(X == 0)
+
+
+def test_padding_rows_untouched():
+    for m, ib in ((37, 0), (150, 32)):
+        for cx in (False, True):
+            L, B = W.problem(9, m, 20, cx)
+            X, _, pad = run(L, B, 1.0, block_size=ib, ldb=m + 11)
+            assert np.all(pad == W.PAD_SENTINEL), (m, cx)
+            check(L, B, X, 1.0, tag=("pad", m, cx))
+
+
+def test_leading_dimension_of_L():
+    for m, ib in ((50, 0), (260, 64)):
+        for cx in (False, True):
+            L, B = W.problem(10, m, 30, cx)
+            X, _, _ = run(L, B, 1.0, block_size=ib, lda=m + 9)
+            check(L, B, X, 1.0, tag=("lda", m, cx))
+
+
+def test_deterministic_repeats():
+    for m, ib in ((48, 0), (400, 64)):
+        L, B = W.problem(11, m, 100, True)
+        X0, _, _ = run(L, B, 1.0, block_size=ib)
+        for _ in range(5):
+            X1, _, _ = run(L, B, 1.0, block_size=ib)
+            assert X1.tobytes() == X0.tobytes()
