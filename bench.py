@@ -1,23 +1,28 @@
 #!/usr/bin/env python3
 """Throughput benchmark of the gfx950 TRSM library.
 
-Default workload: one large real solve, m = n = 16384, FP64, alpha = -1,
-non-unit L with l_ij ~ U(-1,1)/m below the diagonal and l_ii ~ U(1,2),
-B ~ N(0,1), seed 2 -- the configuration the FP64-peak target is stated on.
-A "step" is one complete solve through the blocked path (diagonal-block
-inversion, recursive matrix-core updates, in-place diagonal solves).  Inputs
-are resident in HBM before timing starts; every step re-solves in place.
+Default workload (large_real): one real solve, m = n = 16384, FP64,
+alpha = -1, non-unit L with l_ij ~ U(-1,1)/m below the diagonal and
+l_ii ~ U(1,2), B ~ N(0,1), seed 2 -- the configuration the FP64-peak target is
+stated on.  A "step" is one complete solve through the blocked path
+(diagonal-block inversion, recursive matrix-core updates, in-place diagonal
+solves) with inputs resident in HBM; every step re-solves B in place.
 
-Other workloads (--workload): large_complex (m = n = 8192), batched (10 000
-small complex solves), single (m = n = 32 real).
+Other workloads (--workload):
+  large_complex  ZTRSM m = n = 8192, alpha = (-1, 0), seed 2
+  batched        10 000 independent complex solves, m, n ~ U{8..64},
+                 alpha = (1, 0.5), seed 1 (one step = the whole batch,
+                 descriptors resident: hsma_batch_plan_execute)
+  single         DTRSM m = n = 32, alpha = 1, seed 0
 
-Prints one JSON line (see README of the run contract): metric, value
-(GFLOP/s), roofline of the dominant kernel (measured with HIP events on the
-launch stream), and the CPU oracle timed on a bounded column sample.
+Prints one JSON line: metric/value (GFLOP/s), the roofline of the dominant
+kernel measured with HIP events on its launch stream, rocBLAS on the same GPU
+and inputs, and the CPU oracle timed on a bounded sample of the same work.
 """
 from __future__ import annotations
 
 import argparse
+import ctypes
 import json
 import os
 import sys
@@ -41,11 +46,13 @@ def parse():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="large_real",
-                    choices=["large_real", "large_complex", "single"])
+                    choices=["large_real", "large_complex", "batched", "single"])
     ap.add_argument("--ib", type=int, default=0, help="force I_B (0 = tuning table)")
     ap.add_argument("--m", type=int, default=0, help="override m (and n) for sweeps")
     ap.add_argument("--n", type=int, default=0)
+    ap.add_argument("--count", type=int, default=0, help="batched: number of problems")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-rocblas", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target CPU time of the oracle sample")
     ap.add_argument("--no-check", action="store_true", help="skip the sampled parity check")
@@ -56,34 +63,76 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def main():
-    args = parse()
-    if args.gpus != 1:
-        print(f"bench.py: this build measures one GPU only (got --gpus {args.gpus}); "
-              "columns of B shard across GPUs with L broadcast once, which is not built here.",
-              file=sys.stderr)
-        sys.exit(2)
+# ---------------------------------------------------------------------------
+# rocBLAS on the same GPU (comparison only; called through its public C API)
+# ---------------------------------------------------------------------------
+class RocBlas:
+    SIDE_LEFT, FILL_LOWER, OP_NONE, DIAG_NON_UNIT, DIAG_UNIT = 141, 122, 111, 131, 132
 
-    import torch
-    import paper_2608_25469_amd as hs
+    def __init__(self, stream_handle):
+        self.lib = ctypes.CDLL("librocblas.so")
+        self.h = ctypes.c_void_p()
+        st = self.lib.rocblas_create_handle(ctypes.byref(self.h))
+        if st != 0:
+            raise RuntimeError(f"rocblas_create_handle: {st}")
+        self.lib.rocblas_set_stream(self.h, ctypes.c_void_p(stream_handle))
+        vp, i32 = ctypes.c_void_p, ctypes.c_int32
+        for f in (self.lib.rocblas_dtrsm, self.lib.rocblas_ztrsm):
+            f.argtypes = [vp, i32, i32, i32, i32, i32, i32, vp, vp, i32, vp, i32]
+            f.restype = i32
 
-    if not torch.cuda.is_available():
-        print("bench.py needs a GPU", file=sys.stderr)
-        sys.exit(1)
-    torch.cuda.set_device(0)
-    hs.lib()
+    def trsm(self, L, B, alpha, unit=False):
+        import torch
+        import paper_2608_25469_amd as hs
+        m, n = B.shape
+        cx = B.dtype == torch.complex128
+        a = (ctypes.c_double * 2)(complex(alpha).real, complex(alpha).imag)
+        f = self.lib.rocblas_ztrsm if cx else self.lib.rocblas_dtrsm
+        st = f(self.h, self.SIDE_LEFT, self.FILL_LOWER, self.OP_NONE,
+               self.DIAG_UNIT if unit else self.DIAG_NON_UNIT, m, n, a,
+               ctypes.c_void_p(L.data_ptr()), hs.leading_dim(L),
+               ctypes.c_void_p(B.data_ptr()), hs.leading_dim(B))
+        if st != 0:
+            raise RuntimeError(f"rocblas trsm: {st}")
 
-    if args.workload == "large_real":
-        cfg = dict(W.LARGE_REAL)
-    elif args.workload == "large_complex":
-        cfg = dict(W.LARGE_COMPLEX)
-    else:
-        cfg = dict(W.SINGLE_SMALL)
-    if args.m:
-        cfg["m"] = args.m
-        cfg["n"] = args.n or args.m
+
+def time_gpu(fn, steps, warmup, torch):
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t) * 1e3 / steps
+
+
+def cpu_oracle_columns(L, B, alpha, target_s, complex_):
+    """Oracle on a growing column sample until it takes about target_s."""
+    import oracle
+    n = B.shape[1]
+    rng = np.random.default_rng(123)
+    k = 2
+    while True:
+        cols = rng.choice(n, size=min(k, n), replace=False)
+        Bs = np.asfortranarray(B[:, cols])
+        t1 = time.perf_counter()
+        oracle.solve(L, Bs, alpha)
+        dt = time.perf_counter() - t1
+        if dt * 4 > target_s or k >= n:
+            break
+        k = min(n, max(k * 2, int(k * target_s / max(dt, 1e-3) / 1.2)))
+    gf = W.flops(L.shape[0], len(cols), complex_) / dt / 1e9
+    return {"value": round(gf, 3), "unit": "GFLOP/s", "cores": min(oracle.num_threads(), len(cols)),
+            "kind": "oracle", "seconds": round(dt, 2),
+            "sample": f"{len(cols)} of {n} columns of the same solve (columns are independent)"}
+
+
+# ---------------------------------------------------------------------------
+# Workloads
+# ---------------------------------------------------------------------------
+def run_single_problem(args, torch, hs, cfg):
     m, n, cx, alpha, seed = cfg["m"], cfg["n"], cfg["complex_"], cfg["alpha"], cfg["seed"]
-
     t0 = time.time()
     L, B = W.problem(seed, m, n, cx)
     log(f"inputs m={m} n={n} complex={cx} generated in {time.time() - t0:.1f}s")
@@ -91,116 +140,235 @@ def main():
     Bd = hs.to_colmajor(B)
     torch.cuda.synchronize()
 
-    stream = torch.cuda.current_stream()
-    # First solve: parity on sampled columns against the oracle.
     _, rep = hs.trsm(Ld, Bd, alpha, block_size=args.ib, report=True)
     torch.cuda.synchronize()
     parity = None
-    cols = np.unique(np.linspace(0, n - 1, num=min(n, 8)).astype(int))
     if not args.no_check:
         import oracle
+        cols = np.unique(np.linspace(0, n - 1, num=min(n, 8)).astype(int))
         Xs = np.asfortranarray(Bd[:, cols.tolist()].cpu().numpy())
         Bs = np.asfortranarray(B[:, cols])
-        t1 = time.time()
         ref = oracle.solve(L, Bs, alpha)
         rel = oracle.rel_err_fro(Xs, ref)
         eta = oracle.backward_error(L, Xs, Bs, alpha)
+        bound = 10 * m * 2.0 ** -53
         parity = {"sampled_columns": int(len(cols)), "rel_err_fro": rel, "backward_error": eta,
-                  "bound": 10 * m * 2.0 ** -53, "ok": bool(rel <= 1e-12 and eta <= 10 * m * 2.0 ** -53)}
-        log(f"parity on {len(cols)} columns: rel={rel:.2e} eta={eta:.2e} ({time.time() - t1:.1f}s)")
+                  "bound": bound, "ok": bool(rel <= 1e-12 and eta <= bound)}
+        log(f"parity on {len(cols)} columns: rel={rel:.2e} eta={eta:.2e}")
 
     for _ in range(args.warmup):
         hs.trsm(Ld, Bd, alpha, block_size=args.ib)
     torch.cuda.synchronize()
-
-    # Timed region: K solves, bracketed by synchronisation; phase events live.
-    prof = (hs.PhaseStat * hs.PHASE_COUNT)()
-    hs.lib().hsma_profile_begin()
+    hs.profile_begin()
     torch.cuda.synchronize()
     ts = time.perf_counter()
     for _ in range(args.steps):
         hs.trsm(Ld, Bd, alpha, block_size=args.ib)
     torch.cuda.synchronize()
     te = time.perf_counter()
-    hs.lib().hsma_profile_end(prof, hs.PHASE_COUNT)
-    ms_per_step = (te - ts) * 1e3 / args.steps
+    prof = hs.profile_end()
+    ms = (te - ts) * 1e3 / args.steps
     fl = W.flops(m, n, cx)
-    gflops = fl / (ms_per_step * 1e-3) / 1e9
-    phases = {name: {"launches": int(prof[i].launches) // args.steps,
-                     "ms_per_step": prof[i].ms / args.steps,
-                     "share": None}
-              for i, name in enumerate(hs.PHASE_NAMES)}
-    busy = sum(prof[i].ms for i in range(hs.PHASE_COUNT))
-    for i, name in enumerate(hs.PHASE_NAMES):
-        phases[name]["share"] = (prof[i].ms / busy) if busy > 0 else None
 
-    # Dominant kernel: the trailing-update product (FP64 matrix cores).
-    up = prof[hs.PHASE_UPDATE]
-    if rep["path"] == 2 and up.launches > 0:
-        avg_ms = up.ms / up.launches
-        achieved = (up.flops / up.launches) / (avg_ms * 1e-3) / 1e12
-        roof = {"bound": "mfma", "kernel": "hsma_gemm (update role)",
-                "achieved": round(achieved, 3), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(achieved / FP64_PEAK_TFLOPS, 4), "traffic": None,
-                "avg_launch_ms": avg_ms, "launches_per_step": int(up.launches) // args.steps,
-                "flops_per_launch": up.flops / up.launches}
+    phases = {}
+    busy = sum(v["ms"] for v in prof.values())
+    for k, v in prof.items():
+        phases[k] = {"launches_per_step": v["launches"] // args.steps, "ms_per_step": v["ms"] / args.steps,
+                     "share": v["ms"] / busy if busy else None}
+    if rep["path"] == 2:
+        up = prof["update"]
+        avg = up["ms"] / up["launches"]
+        ach = (up["flops"] / up["launches"]) / (avg * 1e-3) / 1e12
+        roof = {"bound": "mfma", "kernel": "hsma_gemm (trailing-update role)", "achieved": round(ach, 3),
+                "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": round(ach / FP64_PEAK_TFLOPS, 4),
+                "traffic": None, "avg_launch_ms": avg, "launches_per_step": up["launches"] // args.steps,
+                "flops_per_launch": up["flops"] / up["launches"],
+                "per_unit": "2 flops per real multiply-add of C -= A B (complex: its real expansion)"}
     else:
-        sm = prof[hs.PHASE_SMALL]
-        avg_ms = sm.ms / max(1, sm.launches)
+        sm = prof["small"]
+        avg = sm["ms"] / max(1, sm["launches"])
         byts = W.algorithmic_bytes(m, n, cx)
-        roof = {"bound": "hbm", "kernel": "hsma_small_solve",
-                "achieved": round(byts / (avg_ms * 1e-3) / 1e9, 3), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(byts / (avg_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 5),
-                "traffic": None, "avg_launch_ms": avg_ms}
+        ach = byts / (avg * 1e-3) / 1e9
+        roof = {"bound": "hbm", "kernel": "hsma_small_solve", "achieved": round(ach, 3),
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 6),
+                "traffic": None, "avg_launch_ms": avg,
+                "per_unit": "bytes: lower triangle of L once, B read and written once"}
 
-    # CPU baseline: the oracle on a bounded sample of columns of the same solve.
+    rocblas = None
+    if not args.no_rocblas:
+        try:
+            rb = RocBlas(torch.cuda.current_stream().cuda_stream)
+            Bd2 = hs.to_colmajor(B)
+            rms = time_gpu(lambda: rb.trsm(Ld, Bd2, alpha), max(2, args.steps), 1, torch)
+            rocblas = {"ms_per_step": round(rms, 4), "gflops": round(fl / (rms * 1e-3) / 1e9, 2),
+                       "speedup_ours": round(rms / ms, 3)}
+            del Bd2
+        except Exception as e:  # rocBLAS missing or failing is reported, not fatal
+            rocblas = {"error": str(e)}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_oracle_columns(L, B, alpha, args.cpu_seconds, cx)
+
+    value = fl / (ms * 1e-3) / 1e9
+    return {
+        "value": round(value, 2), "unit": "GFLOP/s", "ms_per_step": round(ms, 4),
+        "dtype": "c128" if cx else "f64",
+        "pct_fp64_peak": round(100 * value / (FP64_PEAK_TFLOPS * 1e3), 2),
+        "extra_config": {"m": m, "n": n, "complex": cx, "path": rep["path"],
+                         "block_size": rep["block_size"], "flops_per_step": fl},
+        "phases": phases, "parity": parity, "roofline": roof, "rocblas": rocblas, "cpu_baseline": cpu,
+    }
+
+
+def run_batched(args, torch, hs, cfg):
+    count = args.count or cfg["count"]
+    t0 = time.time()
+    b = W.batched(seed=cfg["seed"], count=count, lo=cfg["lo"], hi=cfg["hi"],
+                  complex_=cfg["complex_"], alpha=cfg["alpha"])
+    pl, pb, vl, vb = hs.pack_batch(b.L, b.B)
+    pb0 = pb.clone()
+    torch.cuda.synchronize()
+    log(f"batch of {count} generated and packed in {time.time() - t0:.1f}s")
+    probs = [hs.problem_struct(L, B, b.alpha) for L, B in zip(vl, vb)]
+    plan = hs.BatchPlan(probs)
+    plan.execute()
+    torch.cuda.synchronize()
+    parity = None
+    if not args.no_check:
+        import oracle
+        worst_rel = worst_eta = 0.0
+        idx = list(range(0, count, max(1, count // 200)))
+        for i in idx:
+            X = hs.from_colmajor(vb[i])
+            ref = oracle.solve(b.L[i], b.B[i], b.alpha)
+            worst_rel = max(worst_rel, oracle.rel_err_fro(X, ref))
+            worst_eta = max(worst_eta, oracle.backward_error(b.L[i], X, b.B[i], b.alpha) /
+                            (10 * b.shapes[i][0] * 2.0 ** -53))
+        parity = {"sampled_problems": len(idx), "worst_rel_err_fro": worst_rel,
+                  "worst_backward_error_over_bound": worst_eta,
+                  "ok": bool(worst_rel <= 1e-12 and worst_eta <= 1.0)}
+        log(f"parity on {len(idx)} problems: rel<={worst_rel:.2e} eta/bound<={worst_eta:.2e}")
+
+    # Timed: K executions of the whole batch (descriptors resident).
+    stream = torch.cuda.current_stream()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    for _ in range(args.warmup):
+        plan.execute()
+    torch.cuda.synchronize()
+    hs.profile_begin()
+    torch.cuda.synchronize()
+    ts = time.perf_counter()
+    ev0.record(stream)
+    for _ in range(args.steps):
+        plan.execute()
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    te = time.perf_counter()
+    prof = hs.profile_end()
+    ms = (te - ts) * 1e3 / args.steps
+    ev_ms = ev0.elapsed_time(ev1) / args.steps
+    fl = b.total_flops()
+    byts = b.total_bytes()
+    sm = prof["small"]
+    roof = {"bound": "hbm", "kernel": "hsma_small_solve (grouped, persistent)",
+            "achieved": round(byts / (ev_ms * 1e-3) / 1e9, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(byts / (ev_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4), "traffic": None,
+            "bytes_per_step": byts, "event_ms_per_step": ev_ms,
+            "group_launches_per_step": sm["launches"] // args.steps,
+            "mean_group_launch_ms": sm["ms"] / max(1, sm["launches"]),
+            "per_unit": "per problem: lower triangle of L once, B read and written once"}
+
+    # One-shot API (host descriptors uploaded each call) for reference.
+    oneshot_ms = time_gpu(lambda: hs.trsm_batched(probs), max(2, args.steps), 1, torch)
+
+    rocblas = None
+    if not args.no_rocblas:
+        try:
+            rb = RocBlas(torch.cuda.current_stream().cuda_stream)
+            pb.copy_(pb0)
+
+            def rb_loop():
+                for L, B in zip(vl, vb):
+                    rb.trsm(L, B, b.alpha)
+            rms = time_gpu(rb_loop, 2, 1, torch)
+            rocblas = {"kind": "rocblas_ztrsm called once per problem", "ms_per_step": round(rms, 3),
+                       "solves_per_s": round(count / (rms * 1e-3), 1), "speedup_ours": round(rms / ms, 2)}
+        except Exception as e:
+            rocblas = {"error": str(e)}
+
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
-        rng = np.random.default_rng(123)
-        k = 2
-        while True:
-            cols = rng.choice(n, size=min(k, n), replace=False)
-            Bs = np.asfortranarray(B[:, cols])
-            t1 = time.perf_counter()
-            oracle.solve(L, Bs, alpha)
-            dt = time.perf_counter() - t1
-            if dt * 4 > args.cpu_seconds or k >= n:
-                break
-            k = min(n, max(k * 2, int(k * args.cpu_seconds / max(dt, 1e-3) / 1.2)))
-        cpu_gflops = W.flops(m, len(cols), cx) / dt / 1e9
-        cpu = {"value": round(cpu_gflops, 3), "unit": "GFLOP/s", "cores": min(oracle.num_threads(), len(cols)),
-               "kind": "oracle", "seconds": round(dt, 2),
-               "sample": f"{len(cols)} of {n} columns of the same solve (columns are independent)"}
+        # Oracle over a prefix of the batch, about cpu_seconds of work.
+        t1 = time.perf_counter()
+        done = 0
+        fl_done = 0.0
+        while done < count and time.perf_counter() - t1 < args.cpu_seconds:
+            oracle.solve(b.L[done], b.B[done], b.alpha)
+            fl_done += W.flops(*b.shapes[done], True)
+            done += 1
+        dt = time.perf_counter() - t1
+        cpu = {"value": round(fl_done / dt / 1e9, 3), "unit": "GFLOP/s", "cores": oracle.num_threads(),
+               "kind": "oracle", "solves_per_s": round(done / dt, 1), "seconds": round(dt, 2),
+               "sample": f"first {done} of {count} problems, one call each (the oracle's threads "
+                         f"split each problem's columns)"}
+        if done == count:
+            cpu["sample"] = f"all {count} problems"
+    plan.close()
+    value = fl / (ms * 1e-3) / 1e9
+    return {
+        "value": round(value, 2), "unit": "GFLOP/s", "ms_per_step": round(ms, 4), "dtype": "c128",
+        "pct_fp64_peak": round(100 * value / (FP64_PEAK_TFLOPS * 1e3), 3),
+        "solves_per_s": round(count / (ms * 1e-3), 1),
+        "extra_config": {"count": count, "flops_per_step": fl, "bytes_per_step": byts,
+                         "oneshot_ms_per_call": round(oneshot_ms, 4)},
+        "parity": parity, "roofline": roof, "rocblas": rocblas, "cpu_baseline": cpu,
+    }
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py: this build measures one GPU only (got --gpus {args.gpus}); "
+              "multi-GPU sharding (columns of B, L broadcast once) is not built.", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import paper_2608_25469_amd as hs
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    torch.cuda.set_device(0)
+    hs.lib()
+
+    names = {"large_real": "DTRSM left-lower, m=n=16384, FP64, alpha=-1, seed 2",
+             "large_complex": "ZTRSM left-lower, m=n=8192, complex FP64, alpha=(-1,0), seed 2",
+             "batched": "ZTRSM batched: 10000 solves, m,n ~ U{8..64}, alpha=(1,0.5), seed 1",
+             "single": "DTRSM left-lower, m=n=32, FP64, alpha=1, seed 0"}
+    if args.workload == "batched":
+        res = run_batched(args, torch, hs, dict(W.BATCHED))
+        workload = names["batched"] if not args.count else f"ZTRSM batched: {args.count} solves"
+    else:
+        cfg = dict({"large_real": W.LARGE_REAL, "large_complex": W.LARGE_COMPLEX,
+                    "single": W.SINGLE_SMALL}[args.workload])
+        if args.m:
+            cfg["m"], cfg["n"] = args.m, args.n or args.m
+        res = run_single_problem(args, torch, hs, cfg)
+        workload = names[args.workload] if not args.m else \
+            f"{'ZTRSM' if cfg['complex_'] else 'DTRSM'} left-lower m={cfg['m']} n={cfg['n']}"
 
     out = {
-        "metric": METRIC,
-        "value": round(gflops, 2),
-        "unit": "GFLOP/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 4),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "c128" if cx else "f64",
-        "data": "synthetic",
-        "pct_fp64_peak": round(100 * gflops / (FP64_PEAK_TFLOPS * 1e3), 2),
-        "config": {
-            "workload": {"large_real": "DTRSM left-lower, m=n=16384, FP64, alpha=-1, seed 2",
-                         "large_complex": "ZTRSM left-lower, m=n=8192, complex FP64, alpha=-1, seed 2",
-                         "single": "DTRSM left-lower, m=n=32, FP64, alpha=1, seed 0"}[args.workload]
-            if not args.m else f"{'ZTRSM' if cx else 'DTRSM'} m={m} n={n}",
-            "m": m, "n": n, "complex": cx, "path": rep["path"], "block_size": rep["block_size"],
-            "flops_per_step": fl, "flop_convention": "real m^2 n; complex 4 m^2 n + 2 m n",
-            "parallelism": "single GPU",
-        },
-        "phases": phases,
-        "parity": parity,
-        "roofline": roof,
-        "cpu_baseline": cpu,
+        "metric": METRIC, "value": res["value"], "unit": res["unit"], "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": res["ms_per_step"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": res["dtype"], "data": "synthetic",
+        "pct_fp64_peak": res["pct_fp64_peak"],
+        "config": dict({"workload": workload, "parallelism": "single GPU",
+                        "flop_convention": "real m^2 n; complex 4 m^2 n + 2 m n"}, **res["extra_config"]),
     }
+    for k in ("solves_per_s", "phases", "parity", "roofline", "rocblas", "cpu_baseline"):
+        if k in res:
+            out[k] = res[k]
     print(json.dumps(out), flush=True)
 
 

@@ -139,6 +139,53 @@ hsma_status hsma_trsm_ex(hsma_diag diag, int64_t m, int64_t n, const void *alpha
 int32_t hsma_lookup_block_size(hsma_dtype dtype, int64_t m, int64_t n);
 
 
+/* ------------------------------------------------------------------------ */
+/* Batched solves (many independent problems per call)                      */
+/* ------------------------------------------------------------------------ */
+
+/* One problem of a batch: the arguments of hsma_trsm in a struct.  For
+ * HSMA_R64F alpha_im must be 0.  A and B are device pointers. */
+typedef struct {
+    int32_t diag;                /* hsma_diag */
+    int32_t dtype;               /* hsma_dtype */
+    int64_t m, n;
+    double alpha_re, alpha_im;
+    const void *A;
+    int64_t lda;
+    void *B;
+    int64_t ldb;
+} hsma_problem;
+
+/*
+ * hsma_trsm_batched -- solve every problem of `probs` (a HOST array of
+ * `count` descriptors; read before the call returns).  Shapes, data types,
+ * diagonal kinds and alphas may all differ.  Each problem is validated with
+ * the hsma_trsm rules first; on the first invalid one its index goes to
+ * *first_bad (if non-NULL), its status is returned and nothing is enqueued.
+ * Problems with m <= 64 run in a handful of persistent grouped launches
+ * (one per data type, diagonal kind and ceil(m/8)), forked onto
+ * library-owned streams and joined back into `stream`; the rest take the
+ * blocked path in order.  Asynchronous on `stream`.  The problems' B
+ * matrices must not overlap each other or any A.
+ */
+hsma_status hsma_trsm_batched(const hsma_problem *probs, int64_t count, int64_t *first_bad,
+                              hsma_stream_t stream);
+
+/*
+ * A batch prepared once and run many times with the same pointers: create
+ * validates like hsma_trsm_batched, builds the work-item table and copies it
+ * to device memory owned by the plan (synchronously, on the current device).
+ * execute enqueues the whole batch on `stream` (same device as create; no
+ * host-to-device copy).  Executions of one plan must not overlap in time
+ * (they share the plan's work counters).  destroy frees the plan after the
+ * caller has synchronised with its last execution.
+ */
+typedef struct hsma_batch_plan hsma_batch_plan;
+hsma_status hsma_batch_plan_create(const hsma_problem *probs, int64_t count, int64_t *first_bad,
+                                   hsma_batch_plan **plan);
+hsma_status hsma_batch_plan_execute(hsma_batch_plan *plan, hsma_stream_t stream);
+hsma_status hsma_batch_plan_destroy(hsma_batch_plan *plan);
+
 /*
  * Phase accounting (the breakdown of the paper's Sec. 5.3, Table 3).  Between
  * hsma_profile_begin() and hsma_profile_end() every kernel the library

@@ -48,6 +48,14 @@ class TrsmReport(ctypes.Structure):
                 ("reserved", ctypes.c_int32 * 6)]
 
 
+class Problem(ctypes.Structure):
+    _fields_ = [("diag", ctypes.c_int32), ("dtype", ctypes.c_int32),
+                ("m", ctypes.c_int64), ("n", ctypes.c_int64),
+                ("alpha_re", ctypes.c_double), ("alpha_im", ctypes.c_double),
+                ("A", ctypes.c_void_p), ("lda", ctypes.c_int64),
+                ("B", ctypes.c_void_p), ("ldb", ctypes.c_int64)]
+
+
 class PhaseStat(ctypes.Structure):
     _fields_ = [("launches", ctypes.c_int64), ("ms", ctypes.c_double), ("flops", ctypes.c_double)]
 
@@ -80,6 +88,15 @@ def lib():
         L.hsma_version.restype = ctypes.c_char_p
         L.hsma_lookup_block_size.argtypes = [i32, i64, i64]
         L.hsma_lookup_block_size.restype = i32
+        L.hsma_trsm_batched.argtypes = [ctypes.POINTER(Problem), i64, ctypes.POINTER(i64), vp]
+        L.hsma_trsm_batched.restype = i32
+        L.hsma_batch_plan_create.argtypes = [ctypes.POINTER(Problem), i64, ctypes.POINTER(i64),
+                                             ctypes.POINTER(vp)]
+        L.hsma_batch_plan_create.restype = i32
+        L.hsma_batch_plan_execute.argtypes = [vp, vp]
+        L.hsma_batch_plan_execute.restype = i32
+        L.hsma_batch_plan_destroy.argtypes = [vp]
+        L.hsma_batch_plan_destroy.restype = i32
         L.hsma_profile_begin.argtypes = []
         L.hsma_profile_begin.restype = i32
         L.hsma_profile_end.argtypes = [ctypes.POINTER(PhaseStat), ctypes.c_int]
@@ -200,6 +217,103 @@ def trsm(L, B, alpha=1.0, unit: bool = False, block_size: int = 0, path: int = 0
     if report:
         return B, {"path": rep.path, "block_size": rep.block_size}
     return B
+
+
+def problem_struct(L, B, alpha=1.0, unit: bool = False) -> Problem:
+    """Descriptor of one solve for the batched entry points (device tensors)."""
+    code = _dtype_code(B)
+    m, n = B.shape
+    a = complex(alpha)
+    if code == R64F and a.imag != 0:
+        raise ValueError("complex alpha for a real problem")
+    return Problem(UNIT if unit else NON_UNIT, code, m, n, a.real, a.imag,
+                   ctypes.c_void_p(L.data_ptr()), leading_dim(L),
+                   ctypes.c_void_p(B.data_ptr()), leading_dim(B))
+
+
+def _problem_array(problems):
+    arr = (Problem * max(1, len(problems)))()
+    for i, p in enumerate(problems):
+        arr[i] = p if isinstance(p, Problem) else problem_struct(*p)
+    return arr
+
+
+def trsm_batched(problems, stream=None) -> None:
+    """Solve every problem in place.  ``problems``: Problem structs or tuples
+    (L, B, alpha[, unit]) of device tensors.  Raises HsmaError (with
+    ``.first_bad``) if a descriptor is invalid; nothing is enqueued then."""
+    arr = _problem_array(problems)
+    bad = ctypes.c_int64(-1)
+    st = lib().hsma_trsm_batched(arr, len(problems), ctypes.byref(bad),
+                                 ctypes.c_void_p(_stream_handle(stream)))
+    if st != 0:
+        err = HsmaError(st, f"hsma_trsm_batched (first bad problem {bad.value})")
+        err.first_bad = bad.value
+        raise err
+
+
+class BatchPlan:
+    """A batch prepared once (descriptors resident on the device) and run
+    many times: ``plan.execute(stream)``."""
+
+    def __init__(self, problems):
+        arr = _problem_array(problems)
+        bad = ctypes.c_int64(-1)
+        h = ctypes.c_void_p()
+        st = lib().hsma_batch_plan_create(arr, len(problems), ctypes.byref(bad), ctypes.byref(h))
+        if st != 0:
+            err = HsmaError(st, f"hsma_batch_plan_create (first bad problem {bad.value})")
+            err.first_bad = bad.value
+            raise err
+        self._h = h
+
+    def execute(self, stream=None) -> None:
+        _check(lib().hsma_batch_plan_execute(self._h, ctypes.c_void_p(_stream_handle(stream))),
+               "hsma_batch_plan_execute")
+
+    def close(self) -> None:
+        if self._h:
+            _check(lib().hsma_batch_plan_destroy(self._h), "hsma_batch_plan_destroy")
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def pack_batch(Ls, Bs, device="cuda", align_bytes: int = 256):
+    """Copy lists of numpy L and B matrices into two device pools, each
+    matrix column-major at its own 256-byte aligned offset (as if separately
+    allocated).  Returns (pool_L, pool_B, views_L, views_B)."""
+    torch = _torch()
+    cx = np.iscomplexobj(Bs[0])
+    dt = torch.complex128 if cx else torch.float64
+    es = 16 if cx else 8
+    al = max(1, align_bytes // es)
+
+    def layout(mats):
+        offs, pos = [], 0
+        for a in mats:
+            offs.append(pos)
+            pos += a.shape[0] * a.shape[1]
+            pos = (pos + al - 1) // al * al
+        return offs, pos
+
+    def fill(mats):
+        offs, total = layout(mats)
+        host = np.zeros(max(total, 1), dtype=np.complex128 if cx else np.float64)
+        for a, o in zip(mats, offs):
+            host[o:o + a.size] = np.asfortranarray(a).ravel(order="F")
+        pool = torch.from_numpy(host).to(device)
+        views = [pool[o:o + a.shape[0] * a.shape[1]].view(a.shape[1], a.shape[0]).t()
+                 for a, o in zip(mats, offs)]
+        return pool, views
+
+    pl, vl = fill(Ls)
+    pb, vb = fill(Bs)
+    return pl, pb, vl, vb
 
 
 def profile_begin() -> None:

@@ -1,0 +1,328 @@
+// Many independent solves per call (the paper lists batched TRSM as future
+// work, Sec. 6).
+//
+// Problems with m <= 64 become work items -- one per 64-column panel -- of
+// the persistent small-solve kernel.  Items are grouped by (data type,
+// diagonal kind, ceil(m/8)) because each group runs a kernel instance
+// specialised for its row bound; inside a group items are ordered by
+// decreasing cost (longest processing time first).  The item table, with one
+// zeroed work counter per group in front, is uploaded in one copy; the group
+// launches are forked onto library-owned streams so they overlap on the
+// device, and joined back into the caller's stream.  Problems with m > 64
+// take the blocked path one by one on the caller's stream.
+
+#include <algorithm>
+#include <cstring>
+#include <mutex>
+#include <vector>
+
+#include "internal.h"
+
+namespace hsma {
+
+// From api.cpp
+hsma_status validate(int diag, int dtype, int64_t m, int64_t n, const void *alpha, const void *A,
+                     int64_t lda, const void *B, int64_t ldb, bool *quick);
+hsma_status trsm_impl(hsma_diag diag, int64_t m, int64_t n, const void *alpha, const void *A,
+                      int64_t lda, void *B, int64_t ldb, hsma_dtype dtype, int ib_override,
+                      int path, hipStream_t s, int *path_used, int *ib_used);
+
+// From small_d.hip / small_z.hip
+hsma_status launch_small_group_d(bool unit, int nch, const void *items, int count,
+                                 int32_t *counter, int wgs, hipStream_t s);
+hsma_status launch_small_group_z(bool unit, int nch, const void *items, int count,
+                                 int32_t *counter, int wgs, hipStream_t s);
+int small_group_occupancy_d(bool unit, int nch);
+int small_group_occupancy_z(bool unit, int nch);
+size_t small_item_bytes_d();
+
+namespace {
+
+// Must match SmallItem in small_kernels.h (checked at run time by size).
+struct Item {
+    const double *A;
+    double *B;
+    int64_t lda, ldb;
+    int32_t m, ncols;
+    double ar, ai;
+};
+
+constexpr int kGroups = 2 * 2 * 8;  // complex x unit x chunk count
+constexpr int kForkStreams = 8;
+constexpr size_t kHeader = 256;     // kGroups int32 counters, padded
+
+int group_of(bool cx, bool unit, int m) {
+    return ((cx ? 1 : 0) * 2 + (unit ? 1 : 0)) * 8 + ((m + 7) / 8 - 1);
+}
+
+struct DevicePool {
+    bool init = false;
+    hipStream_t fork[kForkStreams] = {};
+    int occ[kGroups] = {};
+    std::mutex mu;
+    // pinned staging ring
+    struct Stage {
+        void *host = nullptr;
+        size_t bytes = 0;
+        hipEvent_t done = nullptr;
+        bool used = false;
+    };
+    Stage stage[4];
+    int next = 0;
+};
+DevicePool g_pools[64];
+
+hsma_status pool_for(DevicePool **out, int *cus) {
+    DeviceInfo di;
+    HSMA_TRY(device_info(&di));
+    DevicePool &p = g_pools[di.device];
+    std::lock_guard<std::mutex> lk(p.mu);
+    if (!p.init) {
+        for (int i = 0; i < kForkStreams; ++i)
+            HSMA_HIP(hipStreamCreateWithFlags(&p.fork[i], hipStreamNonBlocking));
+        for (int g = 0; g < kGroups; ++g) {
+            const bool cx = g >= 16, unit = (g / 8) % 2;
+            const int nch = g % 8 + 1;
+            p.occ[g] = cx ? small_group_occupancy_z(unit, nch) : small_group_occupancy_d(unit, nch);
+        }
+        p.init = true;
+    }
+    *out = &p;
+    *cus = di.num_cus;
+    return HSMA_SUCCESS;
+}
+
+}  // namespace
+
+// The device-resident part of a batch: item table with counters, group
+// extents, and the problems that take the blocked path.
+struct BatchTable {
+    void *dev = nullptr;  // kHeader bytes of counters, then items
+    size_t bytes = 0;
+    int start[kGroups] = {}, count[kGroups] = {};
+    std::vector<hsma_problem> large;
+};
+
+static hsma_status check_all(const hsma_problem *probs, int64_t count, int64_t *first_bad) {
+    if (first_bad) *first_bad = -1;
+    if (count < 0) return HSMA_INVALID_SIZE;
+    if (count > 0 && !probs) return HSMA_INVALID_POINTER;
+    for (int64_t i = 0; i < count; ++i) {
+        const hsma_problem &p = probs[i];
+        double al[2] = {p.alpha_re, p.alpha_im};
+        bool quick = false;
+        hsma_status st = validate(p.diag, p.dtype, p.m, p.n, al, p.A, p.lda, p.B, p.ldb, &quick);
+        if (st == HSMA_SUCCESS && p.dtype == HSMA_R64F && p.alpha_im != 0.0) st = HSMA_INVALID_VALUE;
+        if (st != HSMA_SUCCESS) {
+            if (first_bad) *first_bad = i;
+            return st;
+        }
+    }
+    return HSMA_SUCCESS;
+}
+
+// Host image of the table: counters (zero) then items grouped and sorted.
+static void build_image(const hsma_problem *probs, int64_t count, BatchTable *t,
+                        std::vector<unsigned char> *img) {
+    std::vector<Item> groups[kGroups];
+    std::vector<double> costs[kGroups];
+    for (int64_t i = 0; i < count; ++i) {
+        const hsma_problem &p = probs[i];
+        if (p.m == 0 || p.n == 0) continue;
+        if (p.m > 64) {
+            t->large.push_back(p);
+            continue;
+        }
+        const bool cx = p.dtype == HSMA_C64F, unit = p.diag == HSMA_UNIT;
+        const int g = group_of(cx, unit, (int)p.m);
+        const int es = cx ? 2 : 1;
+        for (int64_t c0 = 0; c0 < p.n; c0 += 64) {
+            Item it;
+            it.A = static_cast<const double *>(p.A);
+            it.B = static_cast<double *>(p.B) + es * c0 * p.ldb;
+            it.lda = p.lda;
+            it.ldb = p.ldb;
+            it.m = (int32_t)p.m;
+            it.ncols = (int32_t)std::min<int64_t>(64, p.n - c0);
+            it.ar = p.alpha_re;
+            it.ai = cx ? p.alpha_im : 0.0;
+            groups[g].push_back(it);
+            costs[g].push_back((double)p.m * p.m * it.ncols + 64.0 * p.m);
+        }
+    }
+    size_t n_items = 0;
+    for (int g = 0; g < kGroups; ++g) n_items += groups[g].size();
+    img->assign(kHeader + n_items * sizeof(Item), 0);
+    size_t pos = 0;
+    for (int g = 0; g < kGroups; ++g) {
+        std::vector<size_t> order(groups[g].size());
+        for (size_t i = 0; i < order.size(); ++i) order[i] = i;
+        std::stable_sort(order.begin(), order.end(),
+                         [&](size_t a, size_t b) { return costs[g][a] > costs[g][b]; });
+        t->start[g] = (int)pos;
+        t->count[g] = (int)order.size();
+        for (size_t i : order) {
+            std::memcpy(img->data() + kHeader + pos * sizeof(Item), &groups[g][i], sizeof(Item));
+            ++pos;
+        }
+    }
+}
+
+// Enqueue the grouped launches (and the large problems) on stream s.
+static hsma_status run_table(const BatchTable &t, hipStream_t s) {
+    DevicePool *pool;
+    int cus = 0;
+    HSMA_TRY(pool_for(&pool, &cus));
+    int ngroups = 0;
+    for (int g = 0; g < kGroups; ++g) ngroups += t.count[g] > 0;
+    if (ngroups > 0) {
+        hipEvent_t fork_ev;
+        HSMA_HIP(hipEventCreateWithFlags(&fork_ev, hipEventDisableTiming));
+        HSMA_HIP(hipEventRecord(fork_ev, s));
+        std::vector<hipEvent_t> joins;
+        int k = 0;
+        hsma_status st = HSMA_SUCCESS;
+        // Largest-row groups first: they hold the longest items.
+        for (int g = kGroups - 1; g >= 0 && st == HSMA_SUCCESS; --g) {
+            if (t.count[g] == 0) continue;
+            hipStream_t fs = ngroups == 1 ? s : pool->fork[k++ % kForkStreams];
+            if (fs != s) HSMA_HIP(hipStreamWaitEvent(fs, fork_ev, 0));
+            const bool cx = g >= 16, unit = (g / 8) % 2;
+            const int nch = g % 8 + 1;
+            const int wgs = std::max(1, std::min(t.count[g], pool->occ[g] * cus));
+            const unsigned char *base = static_cast<const unsigned char *>(t.dev);
+            const void *items = base + kHeader + (size_t)t.start[g] * sizeof(Item);
+            int32_t *counter = reinterpret_cast<int32_t *>(const_cast<unsigned char *>(base)) + g;
+            {
+                ProfScope prof(HSMA_PHASE_SMALL, 0.0, fs);
+                st = cx ? launch_small_group_z(unit, nch, items, t.count[g], counter, wgs, fs)
+                        : launch_small_group_d(unit, nch, items, t.count[g], counter, wgs, fs);
+            }
+            if (fs != s) {
+                hipEvent_t j;
+                HSMA_HIP(hipEventCreateWithFlags(&j, hipEventDisableTiming));
+                HSMA_HIP(hipEventRecord(j, fs));
+                joins.push_back(j);
+            }
+        }
+        for (hipEvent_t j : joins) {
+            HSMA_HIP(hipStreamWaitEvent(s, j, 0));
+            HSMA_HIP(hipEventDestroy(j));
+        }
+        HSMA_HIP(hipEventDestroy(fork_ev));
+        HSMA_TRY(st);
+    }
+    for (const hsma_problem &p : t.large) {
+        double al[2] = {p.alpha_re, p.alpha_im};
+        HSMA_TRY(trsm_impl((hsma_diag)p.diag, p.m, p.n, al, p.A, p.lda, p.B, p.ldb,
+                           (hsma_dtype)p.dtype, 0, 0, s, nullptr, nullptr));
+    }
+    return HSMA_SUCCESS;
+}
+
+// Upload the image through a pinned staging buffer (asynchronous on s).
+static hsma_status upload(const std::vector<unsigned char> &img, void *dev, hipStream_t s) {
+    DevicePool *pool;
+    int cus;
+    HSMA_TRY(pool_for(&pool, &cus));
+    std::lock_guard<std::mutex> lk(pool->mu);
+    DevicePool::Stage &st = pool->stage[pool->next];
+    pool->next = (pool->next + 1) % 4;
+    if (st.used) HSMA_HIP(hipEventSynchronize(st.done));  // previous copy from it finished
+    if (st.bytes < img.size()) {
+        if (st.host) HSMA_HIP(hipHostFree(st.host));
+        st.host = nullptr;
+        size_t want = std::max<size_t>(img.size(), 1 << 20);
+        HSMA_HIP(hipHostMalloc(&st.host, want, hipHostMallocDefault));
+        st.bytes = want;
+    }
+    if (!st.done) HSMA_HIP(hipEventCreateWithFlags(&st.done, hipEventDisableTiming));
+    std::memcpy(st.host, img.data(), img.size());
+    HSMA_HIP(hipMemcpyAsync(dev, st.host, img.size(), hipMemcpyHostToDevice, s));
+    HSMA_HIP(hipEventRecord(st.done, s));
+    st.used = true;
+    return HSMA_SUCCESS;
+}
+
+}  // namespace hsma
+
+struct hsma_batch_plan {
+    hsma::BatchTable table;
+    int device = -1;
+};
+
+extern "C" {
+
+hsma_status hsma_trsm_batched(const hsma_problem *probs, int64_t count, int64_t *first_bad,
+                              hsma_stream_t stream) {
+    using namespace hsma;
+    HSMA_TRY(check_all(probs, count, first_bad));
+    if (count == 0) return HSMA_SUCCESS;
+    if (small_item_bytes_d() != sizeof(Item)) return HSMA_NOT_SUPPORTED;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    BatchTable t;
+    std::vector<unsigned char> img;
+    build_image(probs, count, &t, &img);
+    if (img.size() > kHeader) {
+        HSMA_TRY(ws_alloc(&t.dev, img.size(), s));
+        t.bytes = img.size();
+        hsma_status st = upload(img, t.dev, s);
+        if (st == HSMA_SUCCESS) st = run_table(t, s);
+        hsma_status st2 = ws_free(t.dev, s);
+        return st != HSMA_SUCCESS ? st : st2;
+    }
+    return run_table(t, s);
+}
+
+hsma_status hsma_batch_plan_create(const hsma_problem *probs, int64_t count, int64_t *first_bad,
+                                   hsma_batch_plan **plan) {
+    using namespace hsma;
+    if (!plan) return HSMA_INVALID_POINTER;
+    *plan = nullptr;
+    HSMA_TRY(check_all(probs, count, first_bad));
+    if (small_item_bytes_d() != sizeof(Item)) return HSMA_NOT_SUPPORTED;
+    hsma_batch_plan *p = new hsma_batch_plan();
+    std::vector<unsigned char> img;
+    build_image(probs, count, &p->table, &img);
+    hipError_t e = hipGetDevice(&p->device);
+    if (e == hipSuccess && img.size() > kHeader) {
+        e = hipMalloc(&p->table.dev, img.size());
+        if (e == hipSuccess) e = hipMemcpy(p->table.dev, img.data(), img.size(), hipMemcpyHostToDevice);
+        p->table.bytes = img.size();
+    }
+    if (e != hipSuccess) {
+        if (p->table.dev) (void)hipFree(p->table.dev);
+        delete p;
+        return hip_fail(e);
+    }
+    *plan = p;
+    return HSMA_SUCCESS;
+}
+
+hsma_status hsma_batch_plan_execute(hsma_batch_plan *plan, hsma_stream_t stream) {
+    using namespace hsma;
+    if (!plan) return HSMA_INVALID_POINTER;
+    int dev = -1;
+    HSMA_HIP(hipGetDevice(&dev));
+    if (dev != plan->device) return HSMA_INVALID_VALUE;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (plan->table.dev) {
+        // Counters back to zero (a kernel, so the sequence can be captured).
+        HSMA_TRY(launch_zero(kHeader / sizeof(double), 1, 1, static_cast<double *>(plan->table.dev),
+                             kHeader / sizeof(double), s));
+    }
+    return run_table(plan->table, s);
+}
+
+hsma_status hsma_batch_plan_destroy(hsma_batch_plan *plan) {
+    if (!plan) return HSMA_SUCCESS;
+    hsma_status st = HSMA_SUCCESS;
+    if (plan->table.dev) {
+        hipError_t e = hipFree(plan->table.dev);
+        if (e != hipSuccess) st = hsma::hip_fail(e);
+    }
+    delete plan;
+    return st;
+}
+
+}  // extern "C"

@@ -62,8 +62,24 @@ struct GemmParams {
 
 constexpr int BK = 16;
 
+// Workgroups per CU that the tile's LDS ring allows (160 KB per CU, at most
+// 3); the launch bound then caps registers so that many stay resident.
+__host__ __device__ constexpr int lds_bytes(int bm, int bn) {
+    return 2 * (BK * (bm + 4) + bn * (BK + 1)) * 8;
+}
+__host__ __device__ constexpr int occ_for(int bm, int bn) {
+    return (160 * 1024 / lds_bytes(bm, bn)) >= 3 ? 3 : ((160 * 1024 / lds_bytes(bm, bn)) >= 2 ? 2 : 1);
+}
+
+#ifndef HSMA_UPD_BM
+#define HSMA_UPD_BM 128
+#define HSMA_UPD_BN 128
+#define HSMA_UPD_WM 2
+#define HSMA_UPD_WN 2
+#endif
+
 template <bool CX, int BM, int BN, int WM, int WN, int ROLE>
-__global__ __launch_bounds__(256) void hsma_gemm(const GemmParams p) {
+__global__ __launch_bounds__(256, (occ_for(BM, BN))) void hsma_gemm(const GemmParams p) {
     constexpr int TM = BM / WM, TN = BN / WN;
     constexpr int FM = TM / 16, FN = TN / 16;
     constexpr int LDA_S = BM + 4;    // LDS stride of the A tile (per k)
@@ -103,15 +119,17 @@ __global__ __launch_bounds__(256) void hsma_gemm(const GemmParams p) {
 
     // ---- staging registers ----
     // A: real: BM*BK/2 pairs (2 rows each); complex: BM*BK/4 complex elements.
-    constexpr int A_ITEMS = CX ? (BM * BK / 4) / 256 : (BM * BK / 2) / 256;
-    constexpr int B_ITEMS = (BN * BK / 2) / 256;
-    static_assert(A_ITEMS >= 1 && B_ITEMS >= 1, "tile too small for 256 threads");
+    constexpr int A_TOTAL = CX ? (BM * BK / 4) : (BM * BK / 2);
+    constexpr int B_TOTAL = BN * BK / 2;
+    constexpr int A_ITEMS = (A_TOTAL + 255) / 256;
+    constexpr int B_ITEMS = (B_TOTAL + 255) / 256;
     d2 ra[A_ITEMS], rb[B_ITEMS];
 
     auto load_a = [&](int k0) {
 #pragma unroll
         for (int it = 0; it < A_ITEMS; ++it) {
             const int e = tid + it * 256;
+            if (A_TOTAL % 256 && e >= A_TOTAL) break;
             if (!CX) {
                 // pair e: column kk = e / (BM/2), rows 2*(e % (BM/2)) .. +1
                 const int kk = e / (BM / 2), ii = 2 * (e % (BM / 2));
@@ -159,6 +177,7 @@ __global__ __launch_bounds__(256) void hsma_gemm(const GemmParams p) {
 #pragma unroll
         for (int it = 0; it < A_ITEMS; ++it) {
             const int e = tid + it * 256;
+            if (A_TOTAL % 256 && e >= A_TOTAL) break;
             if (!CX) {
                 const int kk = e / (BM / 2), ii = 2 * (e % (BM / 2));
                 double *dst = &As[buf][kk * LDA_S + ii];
@@ -179,6 +198,7 @@ __global__ __launch_bounds__(256) void hsma_gemm(const GemmParams p) {
 #pragma unroll
         for (int it = 0; it < B_ITEMS; ++it) {
             const int e = tid + it * 256;
+            if (B_TOTAL % 256 && e >= B_TOTAL) break;
             const int jj = e / (BK / 2), kk = 2 * (e % (BK / 2));
             const int gn = n0 + jj, gk = k0 + kk;
             d2 v = {0.0, 0.0};
@@ -197,6 +217,7 @@ __global__ __launch_bounds__(256) void hsma_gemm(const GemmParams p) {
 #pragma unroll
         for (int it = 0; it < B_ITEMS; ++it) {
             const int e = tid + it * 256;
+            if (B_TOTAL % 256 && e >= B_TOTAL) break;
             const int jj = e / (BK / 2), kk = 2 * (e % (BK / 2));
             double *dst = &Bs[buf][jj * LDB_S + kk];
             dst[0] = rb[it].x;
@@ -313,12 +334,15 @@ hsma_status launch_role(GemmParams p, int count, hipStream_t s) {
     if (ROLE == (int)GemmRole::Leaf) {
         // In place: one tile must cover every row so each workgroup reads all
         // K rows of its columns before it writes them.
-        if (p.M <= 128) return launch_t<CX, 128, 64, 2, 2, ROLE>(p, count, s);
-        if (p.M <= 256) return launch_t<CX, 256, 64, 4, 1, ROLE>(p, count, s);
-        if (p.M <= 512) return launch_t<CX, 512, 32, 4, 1, ROLE>(p, count, s);
+        // Narrow column tiles keep >= 2 workgroups per CU busy for typical n.
+        if (p.M <= 128) return launch_t<CX, 128, 32, 4, 1, ROLE>(p, count, s);
+        if (p.M <= 256) return launch_t<CX, 256, 32, 4, 1, ROLE>(p, count, s);
+        if (p.M <= 512) return launch_t<CX, 512, 16, 4, 1, ROLE>(p, count, s);
         return HSMA_NOT_SUPPORTED;
     }
     if (p.M <= 64 && p.N <= 64) return launch_t<CX, 64, 64, 2, 2, ROLE>(p, count, s);
+    if (ROLE == (int)GemmRole::Update)
+        return launch_t<CX, HSMA_UPD_BM, HSMA_UPD_BN, HSMA_UPD_WM, HSMA_UPD_WN, ROLE>(p, count, s);
     return launch_t<CX, 128, 128, 2, 2, ROLE>(p, count, s);
 }
 

@@ -10,25 +10,33 @@ using namespace smallk;
 namespace {
 
 template <bool UNIT>
-hsma_status small_t(int m, int64_t n, cplx alpha, const double *A, int64_t lda, double *B,
-                    int64_t ldb, hipStream_t s) {
-    const int64_t panels = (n + 63) / 64;
-    if (panels > 0x7fffffff) return HSMA_INVALID_SIZE;
-    dim3 grid((unsigned)panels), block(64);
-    switch ((m + 7) / 8) {
-#define HSMA_CASE(N)                                                                              \
-    case N:                                                                                       \
-        hipLaunchKernelGGL((hsma_small_solve<false, N, UNIT>), grid, block, 0, s, A, lda, B, ldb, m, \
-                           n, alpha.re, alpha.im);                                                \
+void small_launch(int nch, dim3 grid, const SmallItem &one, const SmallGroup &grp, hipStream_t s) {
+    switch (nch) {
+#define HSMA_CASE(N)                                                                               \
+    case N:                                                                                        \
+        hipLaunchKernelGGL((hsma_small_solve<false, N, UNIT>), grid, dim3(64), 0, s, one, grp);   \
         break;
         HSMA_CASE(1) HSMA_CASE(2) HSMA_CASE(3) HSMA_CASE(4)
         HSMA_CASE(5) HSMA_CASE(6) HSMA_CASE(7) HSMA_CASE(8)
 #undef HSMA_CASE
         default:
-            return HSMA_INVALID_SIZE;
+            break;
     }
-    HSMA_HIP(hipGetLastError());
-    return HSMA_SUCCESS;
+}
+
+template <bool UNIT>
+const void *small_kernel_ptr(int nch) {
+    switch (nch) {
+        case 1: return (const void *)hsma_small_solve<false, 1, UNIT>;
+        case 2: return (const void *)hsma_small_solve<false, 2, UNIT>;
+        case 3: return (const void *)hsma_small_solve<false, 3, UNIT>;
+        case 4: return (const void *)hsma_small_solve<false, 4, UNIT>;
+        case 5: return (const void *)hsma_small_solve<false, 5, UNIT>;
+        case 6: return (const void *)hsma_small_solve<false, 6, UNIT>;
+        case 7: return (const void *)hsma_small_solve<false, 7, UNIT>;
+        case 8: return (const void *)hsma_small_solve<false, 8, UNIT>;
+    }
+    return nullptr;
 }
 
 template <bool UNIT>
@@ -54,13 +62,46 @@ hsma_status inv_t(int m, int base, int ib, const double *A, int64_t lda, double 
 
 hsma_status launch_small_d(bool unit, int m, int64_t n, cplx alpha, const double *A,
                               int64_t lda, double *B, int64_t ldb, hipStream_t s) {
-    return unit ? small_t<true>(m, n, alpha, A, lda, B, ldb, s)
-                : small_t<false>(m, n, alpha, A, lda, B, ldb, s);
+    const int64_t panels = (n + 63) / 64;
+    if (panels > 0x7fffffff || n > 0x7fffffff) return HSMA_INVALID_SIZE;
+    SmallItem one{A, B, lda, ldb, m, (int32_t)n, alpha.re, alpha.im};
+    SmallGroup none{nullptr, 0, nullptr};
+    const int nch = (m + 7) / 8;
+    if (nch < 1 || nch > 8) return HSMA_INVALID_SIZE;
+    if (unit) small_launch<true>(nch, dim3((unsigned)panels), one, none, s);
+    else small_launch<false>(nch, dim3((unsigned)panels), one, none, s);
+    HSMA_HIP(hipGetLastError());
+    return HSMA_SUCCESS;
+}
+
+// Persistent grouped launch over `grp` (device table) with `wgs` workgroups.
+hsma_status launch_small_group_d(bool unit, int nch, const void *grp_items, int count,
+                                    int32_t *counter, int wgs, hipStream_t s) {
+    SmallItem one{};
+    SmallGroup grp{static_cast<const SmallItem *>(grp_items), count, counter};
+    if (nch < 1 || nch > 8 || wgs < 1) return HSMA_INVALID_SIZE;
+    if (unit) small_launch<true>(nch, dim3(wgs), one, grp, s);
+    else small_launch<false>(nch, dim3(wgs), one, grp, s);
+    HSMA_HIP(hipGetLastError());
+    return HSMA_SUCCESS;
+}
+
+// Resident wavefronts per CU of the grouped kernel for one chunk count.
+int small_group_occupancy_d(bool unit, int nch) {
+    const void *k = unit ? small_kernel_ptr<true>(nch) : small_kernel_ptr<false>(nch);
+    int blocks = 0;
+    if (!k || hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k, 64, 0) != hipSuccess) {
+        (void)hipGetLastError();
+        return 4;
+    }
+    return blocks > 0 ? blocks : 1;
 }
 
 hsma_status launch_inv_base_d(bool unit, int m, int base, int ib, const double *A,
                                  int64_t lda, double *W, hipStream_t s) {
     return unit ? inv_t<true>(m, base, ib, A, lda, W, s) : inv_t<false>(m, base, ib, A, lda, W, s);
 }
+
+size_t small_item_bytes_d() { return sizeof(SmallItem); }
 
 }  // namespace hsma

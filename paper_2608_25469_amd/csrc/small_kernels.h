@@ -236,14 +236,59 @@ __device__ __forceinline__ void solve_panel(const double *__restrict__ A, int64_
     Panel<CX, 8 * NCH, UNIT>::template solve<false>(A, lda, B, ldb, m, ncols, alpha);
 }
 
-// One wavefront per 64-column panel of B.
+// Work item of the small-solve kernel: one 64-column panel of one problem.
+struct SmallItem {
+    const double *A;
+    double *B;        // first column of the panel
+    int64_t lda, ldb; // element units
+    int32_t m, ncols;
+    double ar, ai;    // alpha
+};
+
+// Device-side descriptor table of a grouped launch: items of one
+// (dtype, unit, chunk-count) group and the counter the persistent
+// workgroups draw from.  The counter is zero when the table is uploaded.
+struct SmallGroup {
+    const SmallItem *items;
+    int32_t count;
+    int32_t *counter;
+};
+
+// Single problem (items == nullptr): workgroup b solves panel b of `one`.
+// Grouped (items != nullptr): a persistent grid; each wavefront takes the
+// next item index from the group's counter until the group is exhausted.
+// Items are sorted by decreasing cost on the host, so the longest panels
+// start first.
 template <bool CX, int NCH, bool UNIT>
-__global__ __launch_bounds__(64) void hsma_small_solve(const double *__restrict__ A, int64_t lda,
-                                                       double *__restrict__ B, int64_t ldb, int m,
-                                                       int64_t n, double ar, double ai) {
-    const int64_t col0 = (int64_t)blockIdx.x * 64;
-    const int ncols = (int)((n - col0) < 64 ? (n - col0) : 64);
-    solve_panel<CX, NCH, UNIT>(A, lda, B + (CX ? 2 : 1) * col0 * ldb, ldb, m, ncols, cplx{ar, ai});
+__global__ __launch_bounds__(64) void hsma_small_solve(SmallItem one, SmallGroup grp) {
+    const int lane = threadIdx.x & 63;
+    for (int it = 0;; ++it) {
+        SmallItem d;
+        if (grp.items == nullptr) {
+            if (it > 0) break;
+            const int64_t col0 = (int64_t)blockIdx.x * 64;
+            d = one;
+            d.B = one.B + (CX ? 2 : 1) * col0 * one.ldb;
+            const int64_t left = (int64_t)one.ncols - col0;  // ncols holds n here
+            d.ncols = (int)(left < 64 ? left : 64);
+        } else {
+            int idx = 0;
+            if (lane == 0) idx = atomicAdd(grp.counter, 1);
+            idx = __builtin_amdgcn_readlane(idx, 0);
+            if (idx >= grp.count) break;
+            d = grp.items[idx];
+        }
+        if (d.ar == 0.0 && d.ai == 0.0) {
+            // alpha = 0: B := 0, neither A nor B is read.
+            if (lane < d.ncols) {
+                double *bc = d.B + (CX ? 2 : 1) * (int64_t)lane * d.ldb;
+                for (int i = 0; i < (CX ? 2 : 1) * d.m; ++i) bc[i] = 0.0;
+            }
+            continue;
+        }
+        Panel<CX, 8 * NCH, UNIT>::template solve<false>(d.A, d.lda, d.B, d.ldb, d.m, d.ncols,
+                                                         cplx{d.ar, d.ai});
+    }
 }
 
 // Phase 1 of the blocked path (paper Sec. 4.3): the diagonal of L is cut

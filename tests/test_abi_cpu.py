@@ -99,3 +99,25 @@ def test_block_size_lookup_rule(lib):
         for m in (65, 100, 128, 181, 1000, 3000, 5000, 20000, 100000):
             for n in (1, 64, 1000, 16384):
                 assert lib.hsma_lookup_block_size(dt, m, n) == expect(dt, m, n), (dt, m, n)
+
+
+def test_batched_validation_without_device(lib):
+    """Every descriptor is checked before anything touches the device."""
+    P = hs.Problem
+    good = P(0, 0, 4, 3, 1.0, 0.0, ctypes.c_void_p(16), 4, ctypes.c_void_p(32), 4)
+    bad_lda = P(0, 0, 4, 3, 1.0, 0.0, ctypes.c_void_p(16), 3, ctypes.c_void_p(32), 4)
+    bad_alpha = P(0, 0, 4, 3, 1.0, 0.5, ctypes.c_void_p(16), 4, ctypes.c_void_p(32), 4)
+    bad_enum = P(0, 9, 4, 3, 1.0, 0.0, ctypes.c_void_p(16), 4, ctypes.c_void_p(32), 4)
+    for probs, idx, st in (([good, bad_lda], 1, 2), ([bad_alpha, good], 0, 1),
+                           ([good, good, bad_enum], 2, 1)):
+        arr = (P * len(probs))(*probs)
+        first = ctypes.c_int64(-7)
+        assert lib.hsma_trsm_batched(arr, len(probs), ctypes.byref(first), None) == st
+        assert first.value == idx
+        plan = ctypes.c_void_p()
+        first.value = -7
+        assert lib.hsma_batch_plan_create(arr, len(probs), ctypes.byref(first), ctypes.byref(plan)) == st
+        assert first.value == idx and not plan.value
+    assert lib.hsma_trsm_batched(None, 3, None, None) == 3
+    assert lib.hsma_trsm_batched(None, -1, None, None) == 2
+    assert lib.hsma_trsm_batched(None, 0, None, None) == 0

@@ -1,0 +1,121 @@
+"""Batched solves on the GPU: every problem against the oracle, the batch
+against one-at-a-time calls (bit for bit), and the plan API."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+hs = pytest.importorskip("paper_2608_25469_amd")
+
+U = 2.0 ** -53
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+    hs.lib()
+
+
+def mixed_problems(seed, count, max_m=64, max_n=64, big=()):
+    rng = np.random.default_rng(seed)
+    probs = []
+    for i in range(count):
+        m = int(rng.integers(1, max_m + 1))
+        n = int(rng.integers(1, max_n + 1))
+        cx = bool(rng.integers(0, 2))
+        unit = bool(rng.integers(0, 4) == 0)
+        L, B = W.problem(seed * 100000 + i, m, n, cx)
+        alpha = complex(rng.uniform(-2, 2), rng.uniform(-1, 1)) if cx else float(rng.uniform(-2, 2))
+        probs.append((L, B, alpha, unit))
+    for j, (m, n, cx) in enumerate(big):
+        L, B = W.problem(seed * 100000 + 90000 + j, m, n, cx)
+        probs.append((L, B, complex(-1, 0.5) if cx else -0.75, False))
+    return probs
+
+
+def to_dev(probs):
+    out = []
+    for L, B, a, u in probs:
+        out.append((hs.to_colmajor(L), hs.to_colmajor(B), a, u))
+    return out
+
+
+def test_batched_matches_oracle_and_single_calls():
+    probs = mixed_problems(1, 300, max_n=150, big=[(100, 30, False), (200, 70, True)])
+    dev = to_dev(probs)
+    hs.trsm_batched(dev)
+    torch.cuda.synchronize()
+    dev1 = to_dev(probs)
+    for L, B, a, u in dev1:
+        hs.trsm(L, B, a, unit=u)
+    torch.cuda.synchronize()
+    for (L, B, a, u), (_, Bd, _, _), (_, Bs, _, _) in zip(probs, dev, dev1):
+        X = hs.from_colmajor(Bd)
+        Xs = hs.from_colmajor(Bs)
+        assert X.tobytes() == Xs.tobytes(), "batched differs from single call"
+        ref = oracle.solve(L, B, a, unit=u)
+        assert oracle.rel_err_fro(X, ref) <= 1e-12
+        assert oracle.backward_error(L, X, B, a, unit=u) <= 10 * B.shape[0] * U
+
+
+def test_batched_workload_subset():
+    """2000 problems drawn like the 10 000-problem complex workload."""
+    b = W.batched(count=2000)
+    pl, pb, vl, vb = hs.pack_batch(b.L, b.B)
+    hs.trsm_batched([(L, B, b.alpha, False) for L, B in zip(vl, vb)])
+    torch.cuda.synchronize()
+    worst = 0.0
+    for i in range(0, 2000, 7):
+        X = hs.from_colmajor(vb[i])
+        ref = oracle.solve(b.L[i], b.B[i], b.alpha)
+        rel = oracle.rel_err_fro(X, ref)
+        eta = oracle.backward_error(b.L[i], X, b.B[i], b.alpha)
+        worst = max(worst, rel)
+        assert rel <= 1e-12 and eta <= 10 * b.shapes[i][0] * U, (i, b.shapes[i], rel, eta)
+
+
+def test_plan_repeats_bitwise():
+    probs = mixed_problems(2, 120)
+    dev_a = to_dev(probs)
+    plan = hs.BatchPlan([hs.problem_struct(*p) for p in dev_a])
+    dev_b = to_dev(probs)
+    hs.trsm_batched(dev_b)
+    plan.execute()
+    torch.cuda.synchronize()
+    for (_, Ba, _, _), (_, Bb, _, _) in zip(dev_a, dev_b):
+        assert hs.from_colmajor(Ba).tobytes() == hs.from_colmajor(Bb).tobytes()
+    # second execution solves again in place: compare with a second one-shot
+    plan.execute()
+    hs.trsm_batched(dev_b)
+    torch.cuda.synchronize()
+    for (_, Ba, _, _), (_, Bb, _, _) in zip(dev_a, dev_b):
+        assert hs.from_colmajor(Ba).tobytes() == hs.from_colmajor(Bb).tobytes()
+    plan.close()
+
+
+def test_batched_alpha_zero_and_empty():
+    L = hs.to_colmajor(np.full((5, 5), np.nan))
+    B = hs.to_colmajor(np.full((5, 3), np.nan))
+    E = hs.colmajor(0, 4, torch.float64)
+    hs.trsm_batched([(L, B, 0.0, False), (L[:0, :0], E, 1.0, False)])
+    torch.cuda.synchronize()
+    assert np.all(hs.from_colmajor(B) == 0)
+
+
+def test_batched_rejects_bad_descriptor_before_enqueue():
+    probs = mixed_problems(3, 5)
+    dev = to_dev(probs)
+    before = [hs.from_colmajor(B).copy() for _, B, _, _ in dev]
+    structs = [hs.problem_struct(*p) for p in dev]
+    structs[3].lda = 0
+    with pytest.raises(hs.HsmaError) as e:
+        hs.trsm_batched(structs)
+    assert e.value.first_bad == 3 and e.value.status == 2
+    torch.cuda.synchronize()
+    for (_, B, _, _), b0 in zip(dev, before):
+        assert np.array_equal(hs.from_colmajor(B), b0, equal_nan=True)
