@@ -96,6 +96,25 @@ class RocBlas:
             raise RuntimeError(f"rocblas trsm: {st}")
 
 
+def measured_traffic(workload, m, n, ib):
+    """HBM bytes per update launch from the committed rocprofv3 FETCH/WRITE
+    measurement, if it was taken on this workload and on the current kernel
+    source; otherwise None."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "gemm_update_dtrsm16384_traffic.json")
+    try:
+        import json as _json
+        rec = _json.load(open(path))
+        src = open(os.path.join(ROOT, rec["source"]), "rb").read()
+    except (OSError, ValueError, KeyError):
+        return None
+    if hashlib.sha256(src).hexdigest() != rec.get("source_sha256"):
+        return None
+    if workload != "large_real" or (m, n) != (16384, 16384) or ib not in (0, 256):
+        return None
+    return rec["hbm_bytes_per_launch"]
+
+
 def time_gpu(fn, steps, warmup, torch):
     for _ in range(warmup):
         fn()
@@ -181,7 +200,8 @@ def run_single_problem(args, torch, hs, cfg):
         ach = (up["flops"] / up["launches"]) / (avg * 1e-3) / 1e12
         roof = {"bound": "mfma", "kernel": "hsma_gemm (trailing-update role)", "achieved": round(ach, 3),
                 "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": round(ach / FP64_PEAK_TFLOPS, 4),
-                "traffic": None, "avg_launch_ms": avg, "launches_per_step": up["launches"] // args.steps,
+                "traffic": measured_traffic(args.workload, m, n, args.ib),
+                "avg_launch_ms": avg, "launches_per_step": up["launches"] // args.steps,
                 "flops_per_launch": up["flops"] / up["launches"],
                 "per_unit": "2 flops per real multiply-add of C -= A B (complex: its real expansion)"}
     else:

@@ -105,18 +105,47 @@ template <bool CX, int MAXM, bool UNIT>
 struct Panel {
     static constexpr int NQ = (MAXM + 15) / 16;
     static constexpr int ES = CX ? 2 : 1;
+    // Packed lower triangle (rows k..MAXM-1 of column k), in doubles.
+    static constexpr int TRI = MAXM * (MAXM + 1) / 2;
+    static __host__ __device__ constexpr int col_off(int k) { return k * MAXM - k * (k - 1) / 2; }
 
+    // Coefficients of column K for the 16-row groups holding rows below K:
+    // lane l takes row 16q + l%16 (clamped into the column) from LDS.
     template <int K>
-    static __device__ __forceinline__ void step(const double *__restrict__ A, int64_t lda, int m,
-                                                int lane, double rr, double ri,
-                                                double (&yr)[MAXM], double (&yi)[MAXM]) {
+    static __device__ __forceinline__ void read_col(const double *Ls, int lane, double (&Lr)[NQ],
+                                                    double (&Li)[NQ]) {
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            Lr[q] = Li[q] = 0.0;
+            if (K < MAXM && 16 * q + 15 > K) {
+                int row = 16 * q + (lane & 15);
+                row = row < K ? K : (row > MAXM - 1 ? MAXM - 1 : row);
+                const int e = col_off(K) + (row - K);
+                if (CX) {
+                    Lr[q] = Ls[2 * e];
+                    Li[q] = Ls[2 * e + 1];
+                } else {
+                    Lr[q] = Ls[e];
+                }
+            }
+        }
+    }
+
+    // Step K: x_K = y_K / l_KK, then rows below K receive -l_iK x_K.  The
+    // coefficients of column K were read from LDS one step earlier (cur);
+    // this step reads those of column K+1 (nxt) before its own arithmetic.
+    template <int K>
+    static __device__ __forceinline__ void step(const double *Ls, int m, int lane, double rr,
+                                                double ri, double (&yr)[MAXM], double (&yi)[MAXM],
+                                                double (&cr)[NQ], double (&ci)[NQ]) {
         if constexpr (K < MAXM) {
+            double nr[NQ], ni[NQ];
             // Each column step is its own basic block (K < m is uniform): this
             // keeps the instruction selector from sinking the step's
             // multiply-adds to their final uses, which would keep every
             // broadcast coefficient of the unrolled body alive at once.
             if (K < m) {
-                // x_k = y_k / l_kk  (multiply by the broadcast reciprocal)
+                read_col<K + 1>(Ls, lane, nr, ni);
                 if (!UNIT) {
                     const double dr = readlane_d(rr, K);
                     if (CX) {
@@ -129,30 +158,9 @@ struct Panel {
                         yr[K] *= dr;
                     }
                 }
-                if constexpr (K + 1 < MAXM) {
-                    // Column K, rows 16q + lane%16 (clamped to m-1), for the
-                    // 16-row groups q that hold rows below K.
-                    double Lr[NQ], Li[NQ];
-#pragma unroll
-                    for (int q = 0; q < NQ; ++q) {
-                        Lr[q] = Li[q] = 0.0;
-                        if (16 * q + 15 > K) {
-                            const int row = 16 * q + (lane & 15);
-                            const int rc = row < m - 1 ? row : m - 1;
-                            const double *p = A + ES * ((int64_t)K * lda + rc);
-                            if (CX) {
-                                const dpair v = *reinterpret_cast<const dpair *>(p);
-                                Lr[q] = v.x;
-                                Li[q] = v.y;
-                            } else {
-                                Lr[q] = p[0];
-                            }
-                        }
-                    }
-                    ApplyRows<CX, MAXM, K, K + 1>::run(yr, yi, Lr, Li, yr[K], yi[K]);
-                }
+                if constexpr (K + 1 < MAXM) ApplyRows<CX, MAXM, K, K + 1>::run(yr, yi, cr, ci, yr[K], yi[K]);
             }
-            step<K + 1>(A, lda, m, lane, rr, ri, yr, yi);
+            step<K + 1>(Ls, m, lane, rr, ri, yr, yi, nr, ni);
         }
     }
 
@@ -213,7 +221,44 @@ struct Panel {
             }
         }
 
-        step<0>(A, lda, m, lane, rr, ri, yr, yi);
+        // Stage the packed lower triangle of L in LDS with direct
+        // global-to-LDS loads (no VGPRs involved).  Each instruction writes a
+        // whole wavefront's width (64 x 16 bytes for complex, 64 x 4 bytes for
+        // real) contiguously from the start of column k's packed segment; the
+        // part past the segment's end lands in the next column's segment,
+        // which that column's own (later, in-order) loads overwrite, or in the
+        // slack after the last column.  Source rows and columns are clamped
+        // to m-1, so no load leaves A; the values of rows or columns >= m are
+        // only ever combined into rows >= m, which are never stored.
+        __shared__ double Ls[ES * TRI + (CX ? 128 : 32)];
+        typedef __attribute__((address_space(3))) void lds_void;
+        const int mc = m - 1;
+#pragma unroll
+        for (int k = 0; k < MAXM; ++k) {
+            const int kc = k < mc ? k : mc;
+            if (CX) {
+                int row = k + lane;
+                row = row < mc ? row : mc;
+                const double *src = A + 2 * ((int64_t)kc * lda + row);
+                __builtin_amdgcn_global_load_lds((const void *)src, (lds_void *)(Ls + 2 * col_off(k)),
+                                                 16, 0, 0);
+            } else {
+#pragma unroll
+                for (int h = 0; h * 32 < MAXM - k; ++h) {
+                    int row = k + 32 * h + (lane >> 1);
+                    row = row < mc ? row : mc;
+                    const char *src = reinterpret_cast<const char *>(A + (int64_t)kc * lda + row) +
+                                      4 * (lane & 1);
+                    __builtin_amdgcn_global_load_lds((const void *)src,
+                                                     (lds_void *)(Ls + col_off(k) + 32 * h), 4, 0, 0);
+                }
+            }
+        }
+        __syncthreads();
+        double cr[NQ], ci[NQ];
+        read_col<0>(Ls, lane, cr, ci);
+        step<0>(Ls, m, lane, rr, ri, yr, yi, cr, ci);
+        __syncthreads();  // LDS is reused by the next item of a persistent wave
 
         if (active) {
 #pragma unroll
