@@ -46,7 +46,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="large_real",
-                    choices=["large_real", "large_complex", "batched", "single"])
+                    choices=["large_real", "large_complex", "batched", "single", "mixed"])
     ap.add_argument("--ib", type=int, default=0, help="force I_B (0 = tuning table)")
     ap.add_argument("--m", type=int, default=0, help="override m (and n) for sweeps")
     ap.add_argument("--n", type=int, default=0)
@@ -347,6 +347,72 @@ def run_batched(args, torch, hs, cfg):
     }
 
 
+def run_mixed(args, torch, hs, cfg):
+    """Mixed precision vs plain FP64 at equal backward error (<= 1e-13) on
+    m = 8192, n = 4096, for kappa_inf(L) of about 1e3, 1e4, 1e5, 1e6."""
+    import oracle
+    m, n = (args.m or cfg["m"]), (args.n or cfg["n"])
+    kappas = [1e3, 1e4, 1e5, 1e6]
+    rows = []
+    fl = W.flops(m, n, False)
+
+    def timed(fn, Bd, Bpristine, reps):
+        ts = []
+        out = None
+        for _ in range(reps):
+            Bd.copy_(Bpristine)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            out = fn()
+            torch.cuda.synchronize()
+            ts.append((time.perf_counter() - t) * 1e3)
+        return min(ts), sum(ts) / len(ts), out
+
+    for kappa in kappas:
+        L, B = W.mixed_problem(m, n, kappa, seed=cfg["seed"])
+        Ld, Bd, Bp = hs.to_colmajor(L), hs.to_colmajor(B), hs.to_colmajor(B)
+        torch.cuda.synchronize()
+        # plain FP64 solve time, then its backward error (separate call)
+        reps = max(2, args.steps)
+        hs.trsm(Ld, Bd, 1.0)
+        t64, a64, _ = timed(lambda: hs.trsm(Ld, Bd, 1.0), Bd, Bp, reps)
+        Bd.copy_(Bp)
+        _, r64 = hs.trsm(Ld, Bd, 1.0, backward_error=True, report=True)
+        tol = max(1e-13, r64["backward_error"])
+        # mixed: FP32 updates, refine until the backward error reaches tol
+        hs.trsm(Ld, Bd, 1.0, mixed=True)
+        tmx, amx, (_, rmx) = timed(lambda: hs.trsm(Ld, Bd, 1.0, mixed=True, refine_steps=-1,
+                                                   refine_tol=tol, report=True), Bd, Bp, reps)
+        # and the mixed solve alone (no refinement), for the kernel-level ratio
+        t32, _, _ = timed(lambda: hs.trsm(Ld, Bd, 1.0, mixed=True), Bd, Bp, reps)
+        Bd.copy_(Bp)
+        hs.trsm(Ld, Bd, 1.0, mixed=True, refine_steps=-1, refine_tol=tol)
+        torch.cuda.synchronize()
+        cols = np.unique(np.linspace(0, n - 1, num=8).astype(int))
+        X = np.asfortranarray(Bd[:, cols.tolist()].cpu().numpy())
+        ref = oracle.solve(L, np.asfortranarray(B[:, cols]), 1.0)
+        eta_or = oracle.backward_error(L, X, np.asfortranarray(B[:, cols]), 1.0)
+        rows.append({"kappa_target": kappa, "scale": W.mixed_scale(m, kappa),
+                     "fp64_ms": round(t64, 3), "fp64_eta": r64["backward_error"],
+                     "mixed_ms": round(tmx, 3), "mixed_eta": rmx["backward_error"],
+                     "mixed_refine_steps": rmx["refine_steps"], "target_eta": tol,
+                     "mixed_solve_only_ms": round(t32, 3),
+                     "speedup_mixed_over_fp64": round(t64 / tmx, 3),
+                     "oracle_eta_sampled": eta_or, "forward_err_vs_oracle": oracle.rel_err_fro(X, ref)})
+        log(f"kappa {kappa:.0e}: fp64 {t64:.2f} ms eta {r64['backward_error']:.2e} | mixed {tmx:.2f} ms "
+            f"({rmx['refine_steps']} steps) eta {rmx['backward_error']:.2e} | solve-only {t32:.2f} ms")
+        del Ld, Bd, Bp
+    first = rows[0]
+    value = fl / (first["mixed_ms"] * 1e-3) / 1e9
+    return {
+        "value": round(value, 2), "unit": "GFLOP/s", "ms_per_step": first["mixed_ms"], "dtype": "f64",
+        "pct_fp64_peak": round(100 * value / (FP64_PEAK_TFLOPS * 1e3), 2),
+        "extra_config": {"m": m, "n": n, "flops_per_solve": fl,
+                         "value_is": "effective GFLOP/s of the mixed mode with refinement at kappa 1e3"},
+        "mixed": rows,
+    }
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -365,7 +431,10 @@ def main():
              "large_complex": "ZTRSM left-lower, m=n=8192, complex FP64, alpha=(-1,0), seed 2",
              "batched": "ZTRSM batched: 10000 solves, m,n ~ U{8..64}, alpha=(1,0.5), seed 1",
              "single": "DTRSM left-lower, m=n=32, FP64, alpha=1, seed 0"}
-    if args.workload == "batched":
+    if args.workload == "mixed":
+        res = run_mixed(args, torch, hs, dict(W.MIXED))
+        workload = "DTRSM mixed precision vs FP64, m=8192, n=4096, kappa_inf ~1e3..1e6, seed 3"
+    elif args.workload == "batched":
         res = run_batched(args, torch, hs, dict(W.BATCHED))
         workload = names["batched"] if not args.count else f"ZTRSM batched: {args.count} solves"
     else:
@@ -386,7 +455,7 @@ def main():
         "config": dict({"workload": workload, "parallelism": "single GPU",
                         "flop_convention": "real m^2 n; complex 4 m^2 n + 2 m n"}, **res["extra_config"]),
     }
-    for k in ("solves_per_s", "phases", "parity", "roofline", "rocblas", "cpu_baseline"):
+    for k in ("solves_per_s", "phases", "parity", "roofline", "rocblas", "cpu_baseline", "mixed"):
         if k in res:
             out[k] = res[k]
     print(json.dumps(out), flush=True)

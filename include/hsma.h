@@ -103,6 +103,15 @@ hsma_status hsma_trsm(hsma_diag diag, int64_t m, int64_t n, const void *alpha,
                       hsma_dtype dtype, hsma_stream_t stream);
 
 
+/* Precision of the blocked path's trailing updates. */
+typedef enum {
+    HSMA_PREC_FP64 = 0,   /* everything in FP64 (FP64 matrix cores) */
+    HSMA_PREC_MIXED = 1   /* trailing updates on the FP32 matrix cores with
+                             FP64 accumulation of the partial sums, FP64
+                             diagonal blocks, then FP64-residual iterative
+                             refinement; real data only */
+} hsma_precision;
+
 /* Options of hsma_trsm_ex.  Zero-initialise and set what you need. */
 typedef struct {
     int32_t block_size;   /* blocked-path diagonal-block edge I_B: 0 = tuning
@@ -110,26 +119,53 @@ typedef struct {
     int32_t path;         /* 0 = automatic (m <= 64 small kernel, else blocked);
                              1 = force the small kernel (requires m <= 64);
                              2 = force the blocked path */
-    int32_t reserved[6];  /* must be zero */
+    int32_t precision;    /* hsma_precision */
+    int32_t refine_steps; /* refinement steps after the first solve, 0..4
+                             (each: FP64 residual R = alpha B0 - L X, a solve
+                             of L D = R in the chosen precision, X += D);
+                             -1 = stop as soon as the backward error is
+                             <= refine_tol (at most 4 steps) */
+    int32_t want_backward_error; /* 1: compute the normwise backward error of
+                             the returned X (an FP64 residual on the GPU) */
+    int32_t use_graph;    /* 1: run the blocked schedule as a HIP graph captured
+                             on first use and replayed while (dtype, diag, m, n,
+                             A, lda, B, ldb, alpha, I_B, precision) repeat; the
+                             graph owns its workspace (hsma_graph_cache_clear
+                             frees it).  Ignored with refinement or the small
+                             path. */
+    int32_t reserved[2];  /* must be zero */
+    double refine_tol;    /* target for refine_steps = -1 (0 means 1e-13) */
 } hsma_trsm_options;
 
 /* What hsma_trsm_ex did (filled before it returns). */
 typedef struct {
     int32_t path;         /* 1 small kernel, 2 blocked path, 0 nothing enqueued */
     int32_t block_size;   /* I_B used by the blocked path, else 0 */
-    int32_t reserved[6];
+    int32_t refine_steps; /* refinement steps taken */
+    int32_t reserved[5];
+    double backward_error;/* ||L X - alpha B0||_inf / (||L|| ||X|| + |alpha| ||B0||)
+                             of the result, or -1 if not computed */
 } hsma_trsm_report;
 
 /*
- * hsma_trsm_ex -- hsma_trsm with explicit options; same operation, arguments,
- * asynchrony and error behaviour.  opts may be NULL (all defaults); report
- * may be NULL.  Unknown option values give HSMA_INVALID_VALUE; forcing the
- * small kernel with m > 64 gives HSMA_NOT_SUPPORTED.
+ * hsma_trsm_ex -- hsma_trsm with explicit options; same operation, arguments
+ * and error behaviour.  opts may be NULL (all defaults); report may be NULL.
+ * Unknown option values give HSMA_INVALID_VALUE; forcing the small kernel
+ * with m > 64 gives HSMA_NOT_SUPPORTED; HSMA_PREC_MIXED with complex data
+ * gives HSMA_NOT_SUPPORTED.
+ * Asynchronous on `stream` unless a backward error is needed
+ * (want_backward_error = 1 or refine_steps = -1): then the call waits for the
+ * stream before returning, because the value decides what happens next.
+ * Refinement and the backward error need device workspace for two m x n
+ * copies (the original right-hand side and the residual).
  */
 hsma_status hsma_trsm_ex(hsma_diag diag, int64_t m, int64_t n, const void *alpha,
                          const void *A, int64_t lda, void *B, int64_t ldb,
                          hsma_dtype dtype, const hsma_trsm_options *opts,
                          hsma_trsm_report *report, hsma_stream_t stream);
+
+/* Destroy every cached graph and its workspace (waits for their work). */
+hsma_status hsma_graph_cache_clear(void);
 
 /*
  * hsma_lookup_block_size -- the I_B the tuning table gives for (dtype, m, n):

@@ -40,12 +40,19 @@ class HsmaError(RuntimeError):
 
 class TrsmOptions(ctypes.Structure):
     _fields_ = [("block_size", ctypes.c_int32), ("path", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 6)]
+                ("precision", ctypes.c_int32), ("refine_steps", ctypes.c_int32),
+                ("want_backward_error", ctypes.c_int32), ("use_graph", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 2),
+                ("refine_tol", ctypes.c_double)]
 
 
 class TrsmReport(ctypes.Structure):
     _fields_ = [("path", ctypes.c_int32), ("block_size", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 6)]
+                ("refine_steps", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5),
+                ("backward_error", ctypes.c_double)]
+
+
+PREC_FP64, PREC_MIXED = 0, 1
 
 
 class Problem(ctypes.Structure):
@@ -97,6 +104,8 @@ def lib():
         L.hsma_batch_plan_execute.restype = i32
         L.hsma_batch_plan_destroy.argtypes = [vp]
         L.hsma_batch_plan_destroy.restype = i32
+        L.hsma_graph_cache_clear.argtypes = []
+        L.hsma_graph_cache_clear.restype = i32
         L.hsma_profile_begin.argtypes = []
         L.hsma_profile_begin.restype = i32
         L.hsma_profile_end.argtypes = [ctypes.POINTER(PhaseStat), ctypes.c_int]
@@ -189,14 +198,19 @@ def _stream_handle(stream) -> int:
 # ---------------------------------------------------------------------------
 
 def trsm(L, B, alpha=1.0, unit: bool = False, block_size: int = 0, path: int = 0,
-         stream=None, report: bool = False):
+         stream=None, report: bool = False, mixed: bool = False, refine_steps: int = 0,
+         backward_error: bool = False, refine_tol: float = 0.0, graph: bool = False):
     """B <- alpha * inv(tril(L)) * B in place (left, lower, no transpose).
 
     L: m x m, B: m x n, both column-major device tensors of the same dtype
     (float64 or complex128).  ``block_size`` forces the blocked path's I_B,
-    ``path`` forces 1 = small kernel or 2 = blocked.  Asynchronous on
-    ``stream`` (default: torch's current stream).  Returns B (and the
-    library's report if ``report``).
+    ``path`` forces 1 = small kernel or 2 = blocked.  ``mixed`` runs the
+    trailing updates on the FP32 matrix cores; ``refine_steps`` (0..4, or -1
+    for "until the backward error is <= refine_tol") adds FP64-residual
+    refinement; ``backward_error`` reports the result's normwise backward
+    error; ``graph`` replays the blocked schedule as a cached HIP graph.  Asynchronous on ``stream`` (default: torch's current stream)
+    unless a backward error is needed.  Returns B (and the library's report
+    if ``report``).
     """
     code = _dtype_code(B)
     if L.dtype != B.dtype:
@@ -206,7 +220,9 @@ def trsm(L, B, alpha=1.0, unit: bool = False, block_size: int = 0, path: int = 0
         raise ValueError("L must be m x m")
     if m and n and (not L.is_cuda or not B.is_cuda):
         raise ValueError("tensors must be on the GPU")
-    opts = TrsmOptions(block_size, path, (ctypes.c_int32 * 6)())
+    opts = TrsmOptions(block_size, path, PREC_MIXED if mixed else PREC_FP64, refine_steps,
+                       1 if backward_error else 0, 1 if graph else 0, (ctypes.c_int32 * 2)(),
+                       refine_tol)
     rep = TrsmReport()
     st = lib().hsma_trsm_ex(UNIT if unit else NON_UNIT, m, n, _alpha_buf(alpha, code),
                             ctypes.c_void_p(L.data_ptr()), leading_dim(L),
@@ -215,7 +231,8 @@ def trsm(L, B, alpha=1.0, unit: bool = False, block_size: int = 0, path: int = 0
                             ctypes.c_void_p(_stream_handle(stream)))
     _check(st, "hsma_trsm_ex")
     if report:
-        return B, {"path": rep.path, "block_size": rep.block_size}
+        return B, {"path": rep.path, "block_size": rep.block_size,
+                   "refine_steps": rep.refine_steps, "backward_error": rep.backward_error}
     return B
 
 
@@ -326,6 +343,10 @@ def profile_end() -> dict:
     _check(lib().hsma_profile_end(stats, PHASE_COUNT), "hsma_profile_end")
     return {PHASE_NAMES[i]: {"launches": stats[i].launches, "ms": stats[i].ms,
                              "flops": stats[i].flops} for i in range(PHASE_COUNT)}
+
+
+def graph_cache_clear() -> None:
+    _check(lib().hsma_graph_cache_clear(), "hsma_graph_cache_clear")
 
 
 def lookup_block_size(complex_: bool, m: int, n: int) -> int:

@@ -1,9 +1,11 @@
 // C ABI entry points: validation, path selection, workspace, errors.
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
 #include <mutex>
+#include <vector>
 
 #include "internal.h"
 #include "tuning_gfx950.h"
@@ -12,7 +14,21 @@ namespace hsma {
 
 size_t blocked_workspace_bytes(bool cx, int64_t m, int ib);
 hsma_status blocked_trsm(bool cx, bool unit, int64_t m, int64_t n, cplx alpha, const double *A,
-                         int64_t lda, double *B, int64_t ldb, int ib, void *ws, hipStream_t s);
+                         int64_t lda, double *B, int64_t ldb, int ib, void *ws, hipStream_t s,
+                         bool mixed);
+hsma_status blocked_trsm_graph(bool cx, bool unit, int64_t m, int64_t n, cplx alpha,
+                               const double *A, int64_t lda, double *B, int64_t ldb, int ib,
+                               bool mixed, hipStream_t s);
+hsma_status blocked_residual(bool cx, bool unit, int64_t m, int64_t n, const double *A, int64_t lda,
+                             const double *X, int64_t ldx, double *R, int64_t ldr, int ib,
+                             hipStream_t s);
+hsma_status launch_scale_copy(const double *S, int64_t lds, double *D, int64_t ldd, int64_t m,
+                              int64_t n, double alpha, hipStream_t s);
+hsma_status launch_axpy(const double *S, int64_t lds, double *D, int64_t ldd, int64_t m, int64_t n,
+                        hipStream_t s);
+hsma_status launch_rowsum_abs(const double *M, int64_t ld, int64_t m, int64_t n, int tri,
+                              double *out, double *partial, hipStream_t s);
+int64_t rowsum_slabs(int64_t n);
 
 namespace {
 thread_local int g_last_hip_error = 0;
@@ -124,25 +140,12 @@ hsma_status validate(int diag, int dtype, int64_t m, int64_t n, const void *alph
     return HSMA_SUCCESS;
 }
 
-hsma_status trsm_impl(hsma_diag diag, int64_t m, int64_t n, const void *alpha, const void *A,
-                      int64_t lda, void *B, int64_t ldb, hsma_dtype dtype, int ib_override,
-                      int path, hipStream_t s, int *path_used, int *ib_used) {
-    bool quick = false;
-    HSMA_TRY(validate(diag, dtype, m, n, alpha, A, lda, B, ldb, &quick));
-    if (path_used) *path_used = 0;
-    if (ib_used) *ib_used = 0;
-    if (quick) return HSMA_SUCCESS;
-    const bool cx = dtype == HSMA_C64F;
-    const bool unit = diag == HSMA_UNIT;
-    const double *a = static_cast<const double *>(alpha);
-    const cplx al{a[0], cx ? a[1] : 0.0};
-    DeviceInfo dev;
-    HSMA_TRY(device_info(&dev));
-    if (!dev.arch_ok) return HSMA_NOT_SUPPORTED;
-    double *Bd = static_cast<double *>(B);
-    const double *Ad = static_cast<const double *>(A);
+// One solve in place (no refinement): small kernel or blocked path.
+static hsma_status solve_once(bool cx, bool unit, int64_t m, int64_t n, cplx al, const double *Ad,
+                              int64_t lda, double *Bd, int64_t ldb, int ib_override, int path,
+                              bool mixed, hipStream_t s, int *path_used, int *ib_used,
+                              bool use_graph = false) {
     if (al.re == 0.0 && al.im == 0.0) return launch_zero(m, n, cx ? 2 : 1, Bd, ldb, s);
-
     const bool small_ok = m <= 64;
     const bool use_small = (path == 1) ? true : (path == 2 ? false : small_ok);
     if (use_small) {
@@ -154,10 +157,126 @@ hsma_status trsm_impl(hsma_diag diag, int64_t m, int64_t n, const void *alpha, c
     if (!valid_block_size(cx, ib)) return HSMA_INVALID_VALUE;
     if (path_used) *path_used = 2;
     if (ib_used) *ib_used = ib;
+    if (use_graph) return blocked_trsm_graph(cx, unit, m, n, al, Ad, lda, Bd, ldb, ib, mixed, s);
     void *ws = nullptr;
     HSMA_TRY(ws_alloc(&ws, blocked_workspace_bytes(cx, m, ib), s));
-    hsma_status st = blocked_trsm(cx, unit, m, n, al, Ad, lda, Bd, ldb, ib, ws, s);
+    hsma_status st = blocked_trsm(cx, unit, m, n, al, Ad, lda, Bd, ldb, ib, ws, s, mixed);
     hsma_status st2 = ws_free(ws, s);
+    return st != HSMA_SUCCESS ? st : st2;
+}
+
+// Normwise backward error from the residual R (real data, on the device):
+// max row sums of |R|, tril(L), X and B0, combined on the host.
+static hsma_status backward_error_host(bool unit, int64_t m, int64_t n, double alpha,
+                                       const double *Ad, int64_t lda, const double *X,
+                                       int64_t ldx, const double *B0, int64_t ldb0,
+                                       const double *R, int64_t ldr, double *sums, double *partial,
+                                       double *lnorm, double *eta, hipStream_t s) {
+    std::vector<double> h(3 * m);
+    if (*lnorm < 0) {
+        HSMA_TRY(launch_rowsum_abs(Ad, lda, m, m, unit ? 2 : 1, sums, partial, s));
+        std::vector<double> hl(m);
+        HSMA_HIP(hipMemcpyAsync(hl.data(), sums, m * sizeof(double), hipMemcpyDeviceToHost, s));
+        HSMA_HIP(hipStreamSynchronize(s));
+        double mx = 0.0;
+        for (double v : hl) mx = (v > mx || std::isnan(v)) ? v : mx;
+        *lnorm = mx;
+    }
+    HSMA_TRY(launch_rowsum_abs(R, ldr, m, n, 0, sums, partial, s));
+    HSMA_TRY(launch_rowsum_abs(X, ldx, m, n, 0, sums + m, partial, s));
+    HSMA_TRY(launch_rowsum_abs(B0, ldb0, m, n, 0, sums + 2 * m, partial, s));
+    HSMA_HIP(hipMemcpyAsync(h.data(), sums, 3 * m * sizeof(double), hipMemcpyDeviceToHost, s));
+    HSMA_HIP(hipStreamSynchronize(s));
+    double r = 0, x = 0, b = 0;
+    for (int64_t i = 0; i < m; ++i) {
+        r = (h[i] > r || std::isnan(h[i])) ? h[i] : r;
+        x = (h[m + i] > x || std::isnan(h[m + i])) ? h[m + i] : x;
+        b = (h[2 * m + i] > b || std::isnan(h[2 * m + i])) ? h[2 * m + i] : b;
+    }
+    const double den = *lnorm * x + std::fabs(alpha) * b;
+    *eta = den > 0 ? r / den : r;
+    return HSMA_SUCCESS;
+}
+
+hsma_status trsm_impl(hsma_diag diag, int64_t m, int64_t n, const void *alpha, const void *A,
+                      int64_t lda, void *B, int64_t ldb, hsma_dtype dtype, int ib_override,
+                      int path, hipStream_t s, int *path_used, int *ib_used,
+                      const hsma_trsm_options *opt, hsma_trsm_report *rep) {
+    bool quick = false;
+    HSMA_TRY(validate(diag, dtype, m, n, alpha, A, lda, B, ldb, &quick));
+    if (path_used) *path_used = 0;
+    if (ib_used) *ib_used = 0;
+    const bool cx = dtype == HSMA_C64F;
+    const bool mixed = opt && opt->precision == HSMA_PREC_MIXED;
+    const int steps = opt ? opt->refine_steps : 0;
+    const bool want_eta = opt && (opt->want_backward_error || opt->refine_steps < 0);
+    if (mixed && cx) return HSMA_NOT_SUPPORTED;
+    if ((steps != 0 || want_eta) && cx) return HSMA_NOT_SUPPORTED;
+    if (quick) {
+        if (rep) rep->backward_error = want_eta ? 0.0 : -1.0;
+        return HSMA_SUCCESS;
+    }
+    const bool unit = diag == HSMA_UNIT;
+    const double *a = static_cast<const double *>(alpha);
+    const cplx al{a[0], cx ? a[1] : 0.0};
+    DeviceInfo dev;
+    HSMA_TRY(device_info(&dev));
+    if (!dev.arch_ok) return HSMA_NOT_SUPPORTED;
+    double *Bd = static_cast<double *>(B);
+    const double *Ad = static_cast<const double *>(A);
+
+    if (steps == 0 && !want_eta)
+        return solve_once(cx, unit, m, n, al, Ad, lda, Bd, ldb, ib_override, path, mixed, s,
+                          path_used, ib_used, opt && opt->use_graph == 1);
+
+    // Refinement / backward error (real data): keep B0, then iterate.
+    const double tol = (opt && opt->refine_tol > 0) ? opt->refine_tol : 1e-13;
+    const int max_steps = steps < 0 ? 4 : steps;
+    void *ws = nullptr;
+    const size_t mn = (size_t)m * n;
+    const size_t slabs = (size_t)std::max<int64_t>(rowsum_slabs(n), rowsum_slabs(m));
+    HSMA_TRY(ws_alloc(&ws, (2 * mn + (3 + slabs) * (size_t)m) * sizeof(double), s));
+    double *B0 = static_cast<double *>(ws);
+    double *R = B0 + mn;
+    double *sums = R + mn;
+    double *partial = sums + 3 * m;
+    hsma_status st = HSMA_SUCCESS;
+    int used = 0;
+    double eta = -1.0, lnorm = -1.0;
+    int ibr = ib_override > 0 ? ib_override : lookup_block_size(false, m, n);
+    if (!valid_block_size(false, ibr)) ibr = 128;
+    if (hipMemcpy2DAsync(B0, m * sizeof(double), Bd, ldb * sizeof(double), m * sizeof(double), n,
+                         hipMemcpyDeviceToDevice, s) != hipSuccess)
+        st = hip_fail(hipGetLastError());
+    if (st == HSMA_SUCCESS)
+        st = solve_once(false, unit, m, n, al, Ad, lda, Bd, ldb, ib_override, path, mixed, s,
+                        path_used, ib_used);
+    while (st == HSMA_SUCCESS) {
+        const bool more = used < max_steps;
+        if (!more && !want_eta) break;
+        // R = alpha B0 - L X
+        st = launch_scale_copy(B0, m, R, m, m, n, al.re, s);
+        if (st == HSMA_SUCCESS) st = blocked_residual(false, unit, m, n, Ad, lda, Bd, ldb, R, m, ibr, s);
+        if (st != HSMA_SUCCESS) break;
+        if (want_eta) {
+            st = backward_error_host(unit, m, n, al.re, Ad, lda, Bd, ldb, B0, m, R, m, sums, partial,
+                                     &lnorm, &eta, s);
+            if (st != HSMA_SUCCESS) break;
+            if (steps < 0 && eta <= tol) break;
+        }
+        if (!more) break;
+        // L D = R, X += D
+        st = solve_once(false, unit, m, n, cplx{1.0, 0.0}, Ad, lda, R, m, ib_override, path, mixed,
+                        s, nullptr, nullptr);
+        if (st == HSMA_SUCCESS) st = launch_axpy(R, m, Bd, ldb, m, n, s);
+        if (st == HSMA_SUCCESS) ++used;
+        if (!want_eta && used >= max_steps) break;
+    }
+    hsma_status st2 = ws_free(ws, s);
+    if (rep) {
+        rep->refine_steps = used;
+        rep->backward_error = eta;
+    }
     return st != HSMA_SUCCESS ? st : st2;
 }
 
@@ -190,7 +309,7 @@ const char *hsma_version(void) { return "0.1.0 gfx950"; }
 hsma_status hsma_trsm(hsma_diag diag, int64_t m, int64_t n, const void *alpha, const void *A,
                       int64_t lda, void *B, int64_t ldb, hsma_dtype dtype, hsma_stream_t stream) {
     return hsma::trsm_impl(diag, m, n, alpha, A, lda, B, ldb, dtype, 0, 0,
-                           static_cast<hipStream_t>(stream), nullptr, nullptr);
+                           static_cast<hipStream_t>(stream), nullptr, nullptr, nullptr, nullptr);
 }
 
 hsma_status hsma_trsm_ex(hsma_diag diag, int64_t m, int64_t n, const void *alpha, const void *A,
@@ -200,15 +319,24 @@ hsma_status hsma_trsm_ex(hsma_diag diag, int64_t m, int64_t n, const void *alpha
     hsma_trsm_options o;
     std::memset(&o, 0, sizeof(o));
     if (opts) o = *opts;
-    if (report) std::memset(report, 0, sizeof(*report));
-    for (int i = 0; i < 6; ++i)
+    if (report) {
+        std::memset(report, 0, sizeof(*report));
+        report->backward_error = -1.0;
+    }
+    for (int i = 0; i < 2; ++i)
         if (o.reserved[i] != 0) return HSMA_INVALID_VALUE;
+    if (o.use_graph != 0 && o.use_graph != 1) return HSMA_INVALID_VALUE;
     if (o.path < 0 || o.path > 2) return HSMA_INVALID_VALUE;
     if (o.block_size != 0 && !hsma::valid_block_size(dtype == HSMA_C64F, o.block_size))
         return HSMA_INVALID_VALUE;
+    if (o.precision != HSMA_PREC_FP64 && o.precision != HSMA_PREC_MIXED) return HSMA_INVALID_VALUE;
+    if (o.refine_steps < -1 || o.refine_steps > 4) return HSMA_INVALID_VALUE;
+    if (o.want_backward_error != 0 && o.want_backward_error != 1) return HSMA_INVALID_VALUE;
+    if (!(o.refine_tol >= 0.0)) return HSMA_INVALID_VALUE;
     int path_used = 0, ib_used = 0;
     hsma_status st = hsma::trsm_impl(diag, m, n, alpha, A, lda, B, ldb, dtype, o.block_size, o.path,
-                                     static_cast<hipStream_t>(stream), &path_used, &ib_used);
+                                     static_cast<hipStream_t>(stream), &path_used, &ib_used, &o,
+                                     report);
     if (report) {
         report->path = path_used;
         report->block_size = ib_used;

@@ -25,7 +25,8 @@ hsma_status validate(int diag, int dtype, int64_t m, int64_t n, const void *alph
                      int64_t lda, const void *B, int64_t ldb, bool *quick);
 hsma_status trsm_impl(hsma_diag diag, int64_t m, int64_t n, const void *alpha, const void *A,
                       int64_t lda, void *B, int64_t ldb, hsma_dtype dtype, int ib_override,
-                      int path, hipStream_t s, int *path_used, int *ib_used);
+                      int path, hipStream_t s, int *path_used, int *ib_used,
+                      const hsma_trsm_options *opt, hsma_trsm_report *rep);
 
 // From small_d.hip / small_z.hip
 hsma_status launch_small_group_d(bool unit, int nch, const void *items, int count,
@@ -215,7 +216,7 @@ static hsma_status run_table(const BatchTable &t, hipStream_t s) {
     for (const hsma_problem &p : t.large) {
         double al[2] = {p.alpha_re, p.alpha_im};
         HSMA_TRY(trsm_impl((hsma_diag)p.diag, p.m, p.n, al, p.A, p.lda, p.B, p.ldb,
-                           (hsma_dtype)p.dtype, 0, 0, s, nullptr, nullptr));
+                           (hsma_dtype)p.dtype, 0, 0, s, nullptr, nullptr, nullptr, nullptr));
     }
     return HSMA_SUCCESS;
 }

@@ -30,6 +30,7 @@ namespace {
 struct Ctx {
     bool cx;
     bool unit;
+    bool mixed = false;  // trailing updates on the FP32 matrix cores
     int64_t m, n;
     cplx alpha;
     const double *A;
@@ -120,7 +121,8 @@ hsma_status update(const Ctx &c, int64_t r1, int64_t r2, int64_t k0, bool touche
     const int es = c.es();
     GemmBatch one;
     const cplx beta = touched ? cplx{1.0, 0.0} : c.alpha;
-    return launch_gemm(c.cx, GemmRole::Update, (int)(es * (r2 - r1)), (int)c.n, (int)(es * (r1 - k0)),
+    return launch_gemm(c.cx, c.mixed ? GemmRole::UpdateMixed : GemmRole::Update,
+                       (int)(es * (r2 - r1)), (int)c.n, (int)(es * (r1 - k0)),
                        cplx{-1.0, 0.0}, c.A + es * (r1 + k0 * c.lda), c.lda, c.B + es * k0,
                        es * c.ldb, beta, c.B + es * r1, es * c.ldb, 0, one, c.s);
 }
@@ -148,8 +150,10 @@ size_t blocked_workspace_bytes(bool cx, int64_t m, int ib) {
 
 // Enqueue the blocked solve.  `ws` must hold blocked_workspace_bytes().
 hsma_status blocked_trsm(bool cx, bool unit, int64_t m, int64_t n, cplx alpha, const double *A,
-                         int64_t lda, double *B, int64_t ldb, int ib, void *ws, hipStream_t s) {
+                         int64_t lda, double *B, int64_t ldb, int ib, void *ws, hipStream_t s,
+                         bool mixed) {
     Ctx c;
+    c.mixed = mixed;
     c.cx = cx;
     c.unit = unit;
     c.m = m;
@@ -167,6 +171,53 @@ hsma_status blocked_trsm(bool cx, bool unit, int64_t m, int64_t n, cplx alpha, c
     const int base = std::min(ib, 64);
     HSMA_TRY(invert_diagonal(c, base));
     return recurse(c, 0, nblk, false);
+}
+
+// R <- R - tril(L) X for the iterative-refinement residual (FP64 products):
+// the same recursion as the solve, with triangle-masked products on the
+// diagonal blocks (only the lower triangle of each block is read; a unit
+// diagonal is taken as 1).
+namespace {
+struct RCtx {
+    bool cx, unit;
+    int64_t m, n;
+    const double *A;
+    int64_t lda;
+    const double *X;
+    int64_t ldx;
+    double *R;
+    int64_t ldr;
+    int ib;
+    hipStream_t s;
+};
+
+hsma_status residual_rec(const RCtx &c, int64_t b0, int64_t nb) {
+    const int es = c.cx ? 2 : 1;
+    GemmBatch one;
+    if (nb == 1) {
+        const int64_t r0 = b0 * c.ib;
+        const int mr = (int)std::min<int64_t>(c.ib, c.m - r0);
+        return launch_gemm(c.cx, GemmRole::Residual, es * mr, (int)c.n, es * mr, cplx{-1.0, 0.0},
+                           c.A + es * (r0 + r0 * c.lda), c.lda, c.X + es * r0, es * c.ldx,
+                           cplx{1.0, 0.0}, c.R + es * r0, es * c.ldr, c.unit ? 2 : 1, one, c.s);
+    }
+    const int64_t h = nb / 2;
+    HSMA_TRY(residual_rec(c, b0, h));
+    const int64_t r1 = (b0 + h) * c.ib, r2 = std::min<int64_t>((b0 + nb) * c.ib, c.m);
+    const int64_t k0 = b0 * c.ib;
+    HSMA_TRY(launch_gemm(c.cx, GemmRole::Residual, (int)(es * (r2 - r1)), (int)c.n,
+                         (int)(es * (r1 - k0)), cplx{-1.0, 0.0}, c.A + es * (r1 + k0 * c.lda), c.lda,
+                         c.X + es * k0, es * c.ldx, cplx{1.0, 0.0}, c.R + es * r1, es * c.ldr, 0, one,
+                         c.s));
+    return residual_rec(c, b0 + h, nb - h);
+}
+}  // namespace
+
+hsma_status blocked_residual(bool cx, bool unit, int64_t m, int64_t n, const double *A, int64_t lda,
+                             const double *X, int64_t ldx, double *R, int64_t ldr, int ib,
+                             hipStream_t s) {
+    RCtx c{cx, unit, m, n, A, lda, X, ldx, R, ldr, ib, s};
+    return residual_rec(c, 0, (m + ib - 1) / ib);
 }
 
 }  // namespace hsma

@@ -346,6 +346,215 @@ hsma_status launch_role(GemmParams p, int count, hipStream_t s) {
     return launch_t<CX, 128, 128, 2, 2, ROLE>(p, count, s);
 }
 
+
+// ---------------------------------------------------------------------------
+// Mixed precision (real data only): the same product with operands rounded to
+// FP32 (round to nearest even) and multiplied on the FP32 matrix cores
+// (v_mfma_f32_16x16x4_f32, twice the FP64 rate on gfx950).  The FP32
+// accumulators are flushed into FP64 accumulators every KCHUNK values of K,
+// so rounding error grows with the chunk length, not with K.  The result and
+// the epilogue are FP64.
+//
+// FP32 16x16x4 layout (measured on gfx950): lane l holds A[l%16][k0 + l/16],
+// B[k0 + l/16][l%16]; result element v of lane l is row 4(l/16) + v -- already
+// the consecutive-rows order, so no row permutation of the A fragment.
+// ---------------------------------------------------------------------------
+typedef float flt4 __attribute__((ext_vector_type(4)));
+
+template <int BM, int BN, int WM, int WN, int KCHUNK>
+__global__ __launch_bounds__(256, 2) void hsma_gemm_f32mfma(const GemmParams p) {
+    constexpr int TM = BM / WM, TN = BN / WN;
+    constexpr int FM = TM / 16, FN = TN / 16;
+    constexpr int LDA_S = BM + 4;
+    constexpr int LDB_S = BK + 1;
+    static_assert(KCHUNK % BK == 0, "chunk of whole stages");
+    __shared__ float As[2][BK * LDA_S];
+    __shared__ float Bs[2][BN * LDB_S];
+
+    const int T = p.tiles_m * p.tiles_n;
+    const int bid = blockIdx.x;
+    const int per = gridDim.x / 8;
+    const int t = (bid % 8) * per + bid / 8;
+    if (t >= T) return;
+    constexpr int GROUP = 8;
+    const int gsz_full = GROUP * p.tiles_n;
+    const int g = t / gsz_full;
+    const int first = g * GROUP;
+    const int gsize = (p.tiles_m - first) < GROUP ? (p.tiles_m - first) : GROUP;
+    const int tm = first + (t % gsz_full) % gsize;
+    const int tn = (t % gsz_full) / gsize;
+    const int batch = blockIdx.y;
+    const int bo = batch / p.inner, bi = batch % p.inner;
+    const double *__restrict__ Ag = p.A + bo * p.a_outer + bi * p.a_inner;
+    const double *__restrict__ Bg = p.B + bo * p.b_outer + bi * p.b_inner;
+    double *__restrict__ Cg = p.C + bo * p.c_outer + bi * p.c_inner;
+
+    const int m0 = tm * BM, n0 = tn * BN;
+    const int M = p.M, N = p.N, K = p.K;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int wm0 = (wave % WM) * TM, wn0 = (wave / WM) * TN;
+
+    constexpr int A_TOTAL = BM * BK / 2, B_TOTAL = BN * BK / 2;
+    constexpr int A_ITEMS = (A_TOTAL + 255) / 256, B_ITEMS = (B_TOTAL + 255) / 256;
+    d2 ra[A_ITEMS], rb[B_ITEMS];
+    auto load_a = [&](int k0) {
+#pragma unroll
+        for (int it = 0; it < A_ITEMS; ++it) {
+            const int e = tid + it * 256;
+            if (A_TOTAL % 256 && e >= A_TOTAL) break;
+            const int kk = e / (BM / 2), ii = 2 * (e % (BM / 2));
+            const int gr = m0 + ii, gc = k0 + kk;
+            d2 v = {0.0, 0.0};
+            if (gc < K) {
+                const double *src = Ag + (int64_t)gc * p.lda + gr;
+                if (gr + 1 < M) v = *reinterpret_cast<const d2 *>(src);
+                else if (gr < M) v.x = src[0];
+                if (p.tri_a) {
+                    if (gr < gc) v.x = 0.0;
+                    if (gr + 1 < gc) v.y = 0.0;
+                    if (p.tri_a == 2) {
+                        if (gr == gc) v.x = 1.0;
+                        if (gr + 1 == gc) v.y = 1.0;
+                    }
+                }
+            }
+            ra[it] = v;
+        }
+    };
+    auto store_a = [&](int buf) {
+#pragma unroll
+        for (int it = 0; it < A_ITEMS; ++it) {
+            const int e = tid + it * 256;
+            if (A_TOTAL % 256 && e >= A_TOTAL) break;
+            const int kk = e / (BM / 2), ii = 2 * (e % (BM / 2));
+            float *dst = &As[buf][kk * LDA_S + ii];
+            dst[0] = (float)ra[it].x;
+            dst[1] = (float)ra[it].y;
+        }
+    };
+    auto load_b = [&](int k0) {
+#pragma unroll
+        for (int it = 0; it < B_ITEMS; ++it) {
+            const int e = tid + it * 256;
+            if (B_TOTAL % 256 && e >= B_TOTAL) break;
+            const int jj = e / (BK / 2), kk = 2 * (e % (BK / 2));
+            const int gn = n0 + jj, gk = k0 + kk;
+            d2 v = {0.0, 0.0};
+            if (gn < N) {
+                const double *src = Bg + (int64_t)gn * p.ldb + gk;
+                if (gk + 1 < K) v = *reinterpret_cast<const d2 *>(src);
+                else if (gk < K) v.x = src[0];
+            }
+            rb[it] = v;
+        }
+    };
+    auto store_b = [&](int buf) {
+#pragma unroll
+        for (int it = 0; it < B_ITEMS; ++it) {
+            const int e = tid + it * 256;
+            if (B_TOTAL % 256 && e >= B_TOTAL) break;
+            const int jj = e / (BK / 2), kk = 2 * (e % (BK / 2));
+            float *dst = &Bs[buf][jj * LDB_S + kk];
+            dst[0] = (float)rb[it].x;
+            dst[1] = (float)rb[it].y;
+        }
+    };
+
+    dbl4 acc[FM][FN];
+    flt4 acc32[FM][FN];
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j) {
+            acc[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
+            acc32[i][j] = flt4{0.f, 0.f, 0.f, 0.f};
+        }
+
+    const int nk = (K + BK - 1) / BK;
+    if (nk > 0) {
+        load_a(0);
+        load_b(0);
+        store_a(0);
+        store_b(0);
+        __syncthreads();
+    }
+    const int lr = lane & 15, lk = lane >> 4;
+    for (int kt = 0; kt < nk; ++kt) {
+        const int buf = kt & 1;
+        if (kt + 1 < nk) {
+            load_a((kt + 1) * BK);
+            load_b((kt + 1) * BK);
+        }
+        const float *as = As[buf];
+        const float *bs = Bs[buf];
+#pragma unroll
+        for (int s = 0; s < BK / 4; ++s) {
+            const int k = 4 * s + lk;
+            float fa[FM], fb[FN];
+#pragma unroll
+            for (int i = 0; i < FM; ++i) fa[i] = as[k * LDA_S + wm0 + 16 * i + lr];
+#pragma unroll
+            for (int j = 0; j < FN; ++j) fb[j] = bs[(wn0 + 16 * j + lr) * LDB_S + k];
+#pragma unroll
+            for (int i = 0; i < FM; ++i)
+#pragma unroll
+                for (int j = 0; j < FN; ++j)
+                    acc32[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[i], fb[j], acc32[i][j], 0, 0, 0);
+        }
+        if ((kt + 1) % (KCHUNK / BK) == 0 || kt + 1 == nk) {
+#pragma unroll
+            for (int i = 0; i < FM; ++i)
+#pragma unroll
+                for (int j = 0; j < FN; ++j) {
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) acc[i][j][v] += (double)acc32[i][j][v];
+                    acc32[i][j] = flt4{0.f, 0.f, 0.f, 0.f};
+                }
+        }
+        if (kt + 1 < nk) {
+            store_a(buf ^ 1);
+            store_b(buf ^ 1);
+        }
+        __syncthreads();
+    }
+
+    const bool beta_zero = (p.beta_re == 0.0);
+#pragma unroll
+    for (int i = 0; i < FM; ++i) {
+#pragma unroll
+        for (int j = 0; j < FN; ++j) {
+            const int col = n0 + wn0 + 16 * j + lr;
+            const int row = m0 + wm0 + 16 * i + 4 * lk;
+            if (col >= N) continue;
+            double *dst = Cg + (int64_t)col * p.ldc + row;
+#pragma unroll
+            for (int h = 0; h < 4; ++h) {
+                if (row + h < M) {
+                    double r = p.alpha_re * acc[i][j][h];
+                    if (!beta_zero) r = __fma_rn(p.beta_re, dst[h], r);
+                    dst[h] = r;
+                }
+            }
+        }
+    }
+}
+
+hsma_status launch_mixed(GemmParams p, int count, hipStream_t s) {
+    // 128 x 64 keeps both accumulator sets within 256 registers (two
+    // workgroups per CU) without spilling.
+    constexpr int BM = 128, BN = 64;
+    p.tiles_m = (p.M + BM - 1) / BM;
+    p.tiles_n = (p.N + BN - 1) / BN;
+    const int64_t T = (int64_t)p.tiles_m * p.tiles_n;
+    const int64_t grid = (T + 7) / 8 * 8;
+    if (grid > 0x7fffffff || count > 65535) return HSMA_INVALID_SIZE;
+    ProfScope prof(HSMA_PHASE_UPDATE, 2.0 * p.M * (double)p.N * p.K * count, s);
+    hipLaunchKernelGGL((hsma_gemm_f32mfma<BM, BN, 2, 2, 256>), dim3((unsigned)grid, count), dim3(256), 0, s, p);
+    HSMA_HIP(hipGetLastError());
+    return HSMA_SUCCESS;
+}
+
 }  // namespace
 
 hsma_status launch_gemm(bool cplx_, GemmRole role, int M, int N, int K, cplx alpha,
@@ -376,6 +585,10 @@ hsma_status launch_gemm(bool cplx_, GemmRole role, int M, int N, int K, cplx alp
     p.c_outer = batch.c_outer;
     p.c_inner = batch.c_inner;
     if (cplx_ && ((M | K) & 1)) return HSMA_INVALID_SIZE;
+    if (role == GemmRole::UpdateMixed) {
+        if (cplx_) return HSMA_NOT_SUPPORTED;
+        return launch_mixed(p, batch.count, s);
+    }
     switch (role) {
         case GemmRole::Update:
             return cplx_ ? launch_role<true, 0>(p, batch.count, s) : launch_role<false, 0>(p, batch.count, s);
@@ -385,6 +598,8 @@ hsma_status launch_gemm(bool cplx_, GemmRole role, int M, int N, int K, cplx alp
             return cplx_ ? launch_role<true, 2>(p, batch.count, s) : launch_role<false, 2>(p, batch.count, s);
         case GemmRole::Residual:
             return cplx_ ? launch_role<true, 3>(p, batch.count, s) : launch_role<false, 3>(p, batch.count, s);
+        default:
+            break;
     }
     return HSMA_INVALID_VALUE;
 }

@@ -81,7 +81,7 @@ struct GemmBatch {
     int count = 1, inner = 1;
     int64_t a_outer = 0, a_inner = 0, b_outer = 0, b_inner = 0, c_outer = 0, c_inner = 0;
 };
-enum class GemmRole { Update = 0, Leaf = 1, Inverse = 2, Residual = 3 };
+enum class GemmRole { Update = 0, Leaf = 1, Inverse = 2, Residual = 3, UpdateMixed = 4 };
 hsma_status launch_gemm(bool cplx_, GemmRole role, int M, int N, int K,
                         cplx alpha, const double *A, int64_t lda, const double *B,
                         int64_t ldb, cplx beta, double *C, int64_t ldc, int tri_a,

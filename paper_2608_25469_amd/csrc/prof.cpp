@@ -36,9 +36,11 @@ hipEvent_t take_event() {
 }
 }  // namespace
 
+bool graph_capture_active();
+
 ProfScope::ProfScope(int phase, double flops, hipStream_t s) : s_(s), idx_(-1) {
     std::lock_guard<std::mutex> lk(g_mu);
-    if (!g_on) return;
+    if (!g_on || graph_capture_active()) return;  // no event nodes inside a captured graph
     Rec r{phase, flops, take_event(), take_event()};
     if (!r.a || !r.b) return;
     if (hipEventRecord(r.a, s) != hipSuccess) return;

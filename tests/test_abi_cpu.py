@@ -74,8 +74,14 @@ def test_ex_option_checks(lib):
         st = lib.hsma_trsm_ex(0, 4, 3, al, ctypes.c_void_p(16), 4, ctypes.c_void_p(32), 4, 0,
                               ctypes.byref(o), None, None)
         assert st == 1, bad
+    for bad in (dict(precision=2), dict(refine_steps=5), dict(refine_steps=-2),
+                dict(want_backward_error=2), dict(refine_tol=-1.0), dict(use_graph=3)):
+        o = hs.TrsmOptions(**bad)
+        st = lib.hsma_trsm_ex(0, 4, 3, al, ctypes.c_void_p(16), 4, ctypes.c_void_p(32), 4, 0,
+                              ctypes.byref(o), None, None)
+        assert st == 1, bad
     o = hs.TrsmOptions()
-    o.reserved[2] = 1
+    o.reserved[1] = 1
     st = lib.hsma_trsm_ex(0, 4, 3, al, ctypes.c_void_p(16), 4, ctypes.c_void_p(32), 4, 0,
                           ctypes.byref(o), None, None)
     assert st == 1

@@ -186,3 +186,31 @@ def test_deterministic_repeats():
         for _ in range(5):
             X1, _, _ = run(L, B, 1.0, block_size=ib)
             assert X1.tobytes() == X0.tobytes()
+
+
+# ---------------------------------------------------------------------------
+# HIP-graph replay of the blocked schedule
+# ---------------------------------------------------------------------------
+def test_graph_replay_matches_eager_every_time():
+    """Capture once, replay several times with eager work in between; every
+    replay must equal the eager solve of the same input bit for bit."""
+    for cx, m, n, ib in ((False, 600, 100, 64), (True, 300, 40, 32)):
+        L, B = W.problem(21, m, n, cx)
+        Ld = hs.to_colmajor(L)
+        Bg = hs.to_colmajor(B)
+        Be = hs.to_colmajor(B)
+        B0 = hs.to_colmajor(B)
+        hs.trsm(Ld, Be, -1.0, block_size=ib)
+        torch.cuda.synchronize()
+        ref = hs.from_colmajor(Be)
+        for rep in range(4):
+            Bg.copy_(B0)
+            hs.trsm(Ld, Bg, -1.0, block_size=ib, graph=True)
+            torch.cuda.synchronize()
+            assert hs.from_colmajor(Bg).tobytes() == ref.tobytes(), (cx, rep)
+            # unrelated eager work between replays
+            Be.copy_(B0)
+            hs.trsm(Ld, Be, -1.0, block_size=ib)
+            torch.cuda.synchronize()
+        check(L, B, hs.from_colmajor(Bg), -1.0, tag=("graph", cx))
+    hs.graph_cache_clear()

@@ -140,6 +140,25 @@ LARGE_COMPLEX = dict(seed=2, m=8192, n=8192, complex_=True, alpha=complex(-1.0, 
 # lower triangle scaled to reach a target condition number.
 MIXED = dict(seed=3, m=8192, n=4096, complex_=False, alpha=1.0)
 
+def mixed_scale(m: int, kappa: float) -> float:
+    """Off-diagonal scale s giving L(s) = D + s N0 an estimated kappa_inf of
+    ``kappa`` (table written by tests/golden/make_mixed_scales.py, which uses
+    only the oracle's solver; sizes 1024 and 8192)."""
+    import json
+    import os
+    path = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                        "tests", "golden", "mixed_scales.json")
+    with open(path) as f:
+        tab = json.load(f)
+    return float(tab[str(m)][f"{kappa:.0e}"]["scale"])
+
+
+def mixed_problem(m: int = 8192, n: int = 4096, kappa: float = 1e3, seed: int = 3):
+    """The mixed-precision workload: the standard real draw with its strict
+    lower triangle scaled so that kappa_inf(L) is about ``kappa``."""
+    return problem(seed, m, n, False, offdiag_scale=mixed_scale(m, kappa))
+
+
 # Batched small complex solves: 10 000 problems, m and n i.i.d. U{8..64},
 # alpha = (1, 0.5), seed 1.
 BATCHED = dict(seed=1, count=10000, lo=8, hi=64, complex_=True, alpha=complex(1.0, 0.5))
