@@ -14,6 +14,13 @@ Other workloads (--workload):
                  alpha = (1, 0.5), seed 1 (one step = the whole batch,
                  descriptors resident: hsma_batch_plan_execute)
   single         DTRSM m = n = 32, alpha = 1, seed 0
+  mixed          DTRSM m = 8192, n = 4096: mixed precision vs FP64 at equal
+                 backward error, kappa(L) ~ 1e3 .. 1e6, seed 3
+  serving        open-loop Poisson arrivals (--rate per s, --duration s) of
+                 requests with m, n log-uniform in [8, 4096] x [1, 512], 30 %
+                 complex, alpha ~ U(-2, 2), inputs drawn on the device from
+                 Philox keys, 32 GiB budget; reports p50/p99 latency from
+                 scheduled arrival to completion and solves/s
 
 Prints one JSON line: metric/value (GFLOP/s), the roofline of the dominant
 kernel measured with HIP events on its launch stream, rocBLAS on the same GPU
@@ -46,7 +53,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="large_real",
-                    choices=["large_real", "large_complex", "batched", "single", "mixed"])
+                    choices=["large_real", "large_complex", "batched", "single", "mixed", "serving"])
     ap.add_argument("--ib", type=int, default=0, help="force I_B (0 = tuning table)")
     ap.add_argument("--m", type=int, default=0, help="override m (and n) for sweeps")
     ap.add_argument("--n", type=int, default=0)
@@ -56,6 +63,9 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target CPU time of the oracle sample")
     ap.add_argument("--no-check", action="store_true", help="skip the sampled parity check")
+    ap.add_argument("--rate", type=float, default=20000.0, help="serving: arrivals per second")
+    ap.add_argument("--duration", type=float, default=12.0, help="serving: seconds of arrivals")
+    ap.add_argument("--streams", type=int, default=0, help="serving: queue streams (0 = default)")
     return ap.parse_args()
 
 
@@ -413,6 +423,139 @@ def run_mixed(args, torch, hs, cfg):
     }
 
 
+def run_serving(args, torch, hs):
+    """Open-loop serving run through the library's request queue."""
+    import bisect
+    rate, duration = args.rate, args.duration
+    warm_s = min(2.0, duration / 4)
+    seed = 4
+    stream = W.serving_stream(seed=seed, rate=rate, duration=duration)
+    N = len(stream)
+    # Requests to verify against the oracle: spread over the run, cheap on the CPU.
+    sample = set()
+    budget_flops = 3e9
+    for i in range(0, N, max(1, N // 400)):
+        r = stream[i]
+        f = W.flops(r.m, r.n, r.complex_)
+        if f <= budget_flops / 40:
+            sample.add(i)
+            budget_flops -= f
+        if budget_flops <= 0 or len(sample) >= 40:
+            break
+    arr = (hs.Request * N)()
+    t_sched = np.array([r.t_arrival for r in stream])
+    for i, r in enumerate(stream):
+        arr[i] = hs.request(r.m, r.n, r.alpha, complex_=r.complex_, key=W.serving_key(seed, r.rid),
+                            release_on_completion=i not in sample)
+    total_flops = sum(W.flops(r.m, r.n, r.complex_) for r in stream)
+    log(f"serving: {N} requests over {duration:.0f} s at {rate:.0f}/s, "
+        f"{total_flops / duration / 1e12:.2f} TFLOP/s offered")
+    L = hs.lib()
+    q = hs.Queue(n_streams=args.streams)
+    # Warm-up (first launches of every kernel family, memory pool growth).
+    wk = [hs.request(m, n, 1.0, complex_=cx, key=W.serving_key(99, k))
+          for k, (m, n, cx) in enumerate([(m, n, cx) for m in (8, 40, 64, 100, 300, 1000, 3000)
+                                          for n in (1, 64, 500) for cx in (False, True)])]
+    for t in q.submit(wk):
+        q.wait(t, 120)
+    rsz = ctypes.sizeof(hs.Request)
+    tickets = (ctypes.c_uint64 * N)()
+    t0 = hs.clock_ns() + 2e6
+    for i in range(N):
+        arr[i].t_arrival_ns = t0 + t_sched[i] * 1e9
+    sched_ns = t0 + t_sched * 1e9
+    submitted = 0
+    last_log = time.time()
+    while submitted < N:
+        now = hs.clock_ns()
+        hi = bisect.bisect_right(sched_ns, now, lo=submitted)
+        if hi > submitted:
+            st = L.hsma_queue_submit(q._h, ctypes.cast(ctypes.addressof(arr) + submitted * rsz,
+                                                       ctypes.POINTER(hs.Request)),
+                                     hi - submitted,
+                                     ctypes.cast(ctypes.addressof(tickets) + submitted * 8,
+                                                 ctypes.POINTER(ctypes.c_uint64)))
+            if st != 0:
+                raise hs.HsmaError(st, "hsma_queue_submit")
+            submitted = hi
+        else:
+            time.sleep(min(2e-4, max(0.0, (sched_ns[submitted] - now) * 1e-9)))
+        if time.time() - last_log > 2.0:
+            s = q.stats()
+            log(f"  t={(now - t0) * 1e-9:5.1f}s submitted {submitted} completed {s['completed']} "
+                f"pending {s['pending']} inflight {s['inflight']}")
+            last_log = time.time()
+    t_end_submit = hs.clock_ns()
+    deadline = time.time() + max(60.0, 4 * duration)
+    while True:
+        s = q.stats()
+        if s["completed"] + s["failed"] >= N + len(wk) or time.time() > deadline:
+            break
+        if time.time() - last_log > 2.0:
+            log(f"  draining: completed {s['completed']} pending {s['pending']} inflight {s['inflight']}")
+            last_log = time.time()
+        time.sleep(0.01)
+    s = q.stats()
+    info = hs.RequestInfo()
+    lat, done_t, arr_t = [], [], []
+    failed = 0
+    for i in range(N):
+        st = L.hsma_queue_poll(q._h, tickets[i], ctypes.byref(info))
+        if st == 0:
+            done_t.append(info.t_done_ns)
+            arr_t.append(info.t_arrival_ns)
+            if t_sched[i] >= warm_s:
+                lat.append(info.t_done_ns - info.t_arrival_ns)
+        elif st != 9:
+            failed += 1
+    lat = np.sort(np.array(lat))
+    done_t = np.array(done_t)
+    completed = len(done_t)
+    span = (done_t.max() - t0) * 1e-9 if completed else float("nan")
+    backlog_s = (done_t.max() - t_end_submit) * 1e-9 if completed else float("nan")
+    # parity on the kept sample
+    parity = None
+    if sample and not args.no_check:
+        import oracle
+        worst = 0.0
+        for i in sorted(sample):
+            r = stream[i]
+            st = L.hsma_queue_poll(q._h, tickets[i], ctypes.byref(info))
+            if st != 0:
+                continue
+            X = hs.matrix_from_pointer(info.B, r.m, r.n, r.m, r.complex_)
+            Lh, Bh = W.synthetic_inputs(r.m, r.n, W.serving_key(seed, r.rid), r.complex_)
+            worst = max(worst, oracle.rel_err_fro(X, oracle.solve(Lh, Bh, r.alpha)))
+            hs.lib().hsma_queue_release(q._h, tickets[i])
+        parity = {"sampled_requests": len(sample), "worst_rel_err_fro": worst, "ok": bool(worst <= 1e-12)}
+        log(f"parity on {len(sample)} served requests: rel <= {worst:.2e}")
+    q.close()
+
+    def pct(p):
+        return float(lat[int(p * (len(lat) - 1) + 0.5)]) * 1e-6 if len(lat) else None
+    solves_per_s = completed / span if completed else 0.0
+    saturated = bool(backlog_s > 0.5)
+    return {
+        "value": round(solves_per_s, 1), "unit": "solves/s",
+        "ms_per_step": round(span * 1e3, 2), "dtype": "f64+c128",
+        "pct_fp64_peak": round(100 * total_flops / span / (FP64_PEAK_TFLOPS * 1e12), 3),
+        "solves_per_s": round(solves_per_s, 1),
+        "serving": {"p50_ms": pct(0.50), "p99_ms": pct(0.99), "max_ms": pct(1.0),
+                    "mean_ms": float(lat.mean()) * 1e-6 if len(lat) else None,
+                    "latency_from": "scheduled arrival to completion event",
+                    "latency_window": f"arrivals after the first {warm_s:.0f} s",
+                    "offered_per_s": rate, "requests": N, "completed": completed, "failed": failed,
+                    "rejected": s["rejected"], "peak_budget_bytes": s["bytes_peak"],
+                    "budget_bytes": 32 << 30, "saturated": saturated,
+                    "drain_after_last_arrival_s": round(backlog_s, 3),
+                    "served_tflops": round(total_flops / span / 1e12, 3)},
+        "extra_config": {"rate_per_s": rate, "duration_s": duration, "seed": seed,
+                         "m_range": [8, 4096], "n_range": [1, 512], "p_complex": 0.3,
+                         "inputs": "generated on the device (Philox4x32-10 keyed by seed and request id)"},
+        "parity": parity,
+    }
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -434,6 +577,10 @@ def main():
     if args.workload == "mixed":
         res = run_mixed(args, torch, hs, dict(W.MIXED))
         workload = "DTRSM mixed precision vs FP64, m=8192, n=4096, kappa_inf ~1e3..1e6, seed 3"
+    elif args.workload == "serving":
+        res = run_serving(args, torch, hs)
+        workload = (f"TRSM serving: Poisson {args.rate:.0f} req/s for {args.duration:.0f} s, m log-U[8,4096], "
+                    f"n log-U[1,512], 70% real / 30% complex, seed 4")
     elif args.workload == "batched":
         res = run_batched(args, torch, hs, dict(W.BATCHED))
         workload = names["batched"] if not args.count else f"ZTRSM batched: {args.count} solves"
@@ -455,7 +602,8 @@ def main():
         "config": dict({"workload": workload, "parallelism": "single GPU",
                         "flop_convention": "real m^2 n; complex 4 m^2 n + 2 m n"}, **res["extra_config"]),
     }
-    for k in ("solves_per_s", "phases", "parity", "roofline", "rocblas", "cpu_baseline", "mixed"):
+    for k in ("solves_per_s", "phases", "parity", "roofline", "rocblas", "cpu_baseline", "mixed",
+              "serving"):
         if k in res:
             out[k] = res[k]
     print(json.dumps(out), flush=True)

@@ -250,6 +250,145 @@ typedef struct {
 hsma_status hsma_profile_begin(void);
 hsma_status hsma_profile_end(hsma_phase_stat *out, int count);
 
+
+/* ------------------------------------------------------------------------ */
+/* Synthetic inputs and the serving queue                                   */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * hsma_generate_inputs -- fill a device L (m x m, lda = m) and B (m x n,
+ * ldb = m) with the standard synthetic workload, drawn on the GPU from the
+ * counter-based generator Philox4x32-10 (Salmon et al., SC'11) under `key`.
+ * Element e (column-major index) of L uses counter (e mod 2^32, e div 2^32,
+ * 0, 0), of B counter (e mod 2^32, e div 2^32, 1, 0); key words (key mod 2^32,
+ * key div 2^32).  The outputs x0..x3 give u1 = ((x1<<32|x0) >> 11) 2^-53 and
+ * u2 = ((x3<<32|x2) >> 11) 2^-53.  L: strict lower (2 u1 - 1)/m (complex
+ * imaginary part (2 u2 - 1)/m), diagonal 1 + u1 (complex imaginary u2 - 1/2),
+ * upper triangle 0.  B: sqrt(-2 ln(1 - u1)) cos(2 pi u2) (complex imaginary
+ * part with sin).  Asynchronous on `stream`.  Errors: bad dtype ->
+ * HSMA_INVALID_VALUE; m < 0 or n < 0 -> HSMA_INVALID_SIZE; m == 0 -> success,
+ * nothing done; L NULL, or B NULL with n > 0 -> HSMA_INVALID_POINTER.
+ */
+hsma_status hsma_generate_inputs(hsma_dtype dtype, int64_t m, int64_t n, uint64_t key, void *L,
+                                 void *B, hsma_stream_t stream);
+
+/*
+ * Serving queue (continuous batching; the paper's Sec. 6 outlook on batched
+ * TRSM carried to a request loop).  Clients submit solve requests at any
+ * time; a scheduler thread owned by the queue
+ *   - retires finished work by polling events, returning its memory budget
+ *     and recording its latency (arrival to completion),
+ *   - admits pending requests strictly in arrival order while the HBM budget
+ *     and the in-flight limit allow,
+ *   - launches each admission round: all its small requests (m <= 64) as one
+ *     batched call (hsma_trsm_batched) on the queue's small stream, every
+ *     larger request as its own blocked solve, round-robin over the queue's
+ *     other streams.
+ * A request's footprint is its blocked-path workspace (a 4 KiB descriptor
+ * share for small requests) plus, for synthetic requests, its L and B.
+ */
+typedef enum { HSMA_BACKEND_HIP = 0, HSMA_BACKEND_SIMULATED = 1 } hsma_backend;
+typedef enum { HSMA_INPUT_DEVICE = 0, HSMA_INPUT_SYNTHETIC = 1 } hsma_input_kind;
+
+typedef struct {
+    int32_t backend;          /* hsma_backend.  HSMA_BACKEND_SIMULATED runs the
+                                 same policy with no device work: each launch
+                                 takes sim_fixed_ns + flops / sim_flops_per_ns
+                                 of modelled time on its stream (flops = m^2 n,
+                                 x4 for complex); for tests of the policy */
+    int32_t n_streams;        /* streams for large requests (0 = 4) */
+    int32_t max_inflight;     /* admitted, unfinished requests (0 = 1024) */
+    int32_t poll_us;          /* completion poll period while work runs (0 = 20) */
+    uint64_t hbm_budget_bytes;/* summed footprint limit (0 = 32 GiB) */
+    double sim_flops_per_ns;  /* simulated rate (<= 0: 40000, i.e. 40 TFLOP/s) */
+    double sim_fixed_ns;      /* simulated per-launch latency */
+} hsma_queue_config;
+
+typedef struct {
+    hsma_problem prob;        /* the solve; for HSMA_INPUT_SYNTHETIC, A, B, lda
+                                 and ldb are ignored (the server allocates
+                                 lda = ldb = m and fills them with
+                                 hsma_generate_inputs under `key`) */
+    int32_t input;            /* hsma_input_kind */
+    int32_t release_on_completion; /* synthetic only: 1 frees L and B as soon
+                                 as the solve finishes (load generation);
+                                 0 keeps them, counted against the budget,
+                                 until hsma_queue_release */
+    uint64_t key;             /* Philox key of a synthetic request */
+    double t_arrival_ns;      /* arrival time on hsma_clock_ns()'s clock for
+                                 the latency figure; <= 0 means "now" (an
+                                 open-loop generator passes the scheduled
+                                 time, so a late submit still counts) */
+} hsma_request;
+
+typedef struct {
+    int32_t status;           /* HSMA_SUCCESS, HSMA_PENDING or the failure */
+    int32_t path;             /* 1 small (batched), 2 blocked, 0 not launched */
+    double t_arrival_ns, t_admit_ns, t_done_ns;
+    const void *A;            /* where L and X live (server memory for a kept */
+    void *B;                  /* synthetic request; the caller's otherwise) */
+    int64_t lda, ldb;
+} hsma_request_info;
+
+typedef struct {
+    int64_t submitted, rejected, completed, failed, pending, inflight;
+    uint64_t bytes_in_use, bytes_peak;  /* budget accounting */
+    double p50_ns, p99_ns, max_ns, mean_ns; /* latency of completed requests;
+                                 percentile q is the sorted sample at rank
+                                 round(q (count - 1)) */
+    double solves_per_s;      /* completed / (last completion - first submit) */
+} hsma_queue_statistics;
+
+typedef struct hsma_queue hsma_queue;
+
+/* Monotonic clock used for arrival and completion times, in ns. */
+double hsma_clock_ns(void);
+
+/* Budget footprint of a request in bytes (what admission reserves for it);
+ * host-only, no validation beyond the pointers. */
+hsma_status hsma_request_footprint(const hsma_request *req, uint64_t *bytes);
+
+/* cfg may be NULL (defaults).  The HIP backend binds the caller's current
+ * device.  Negative counts or an unknown backend -> HSMA_INVALID_VALUE. */
+hsma_status hsma_queue_create(const hsma_queue_config *cfg, hsma_queue **queue);
+
+/*
+ * Submit `count` requests (host array, read before return); tickets[i]
+ * receives request i's ticket.  All or nothing: every request is validated
+ * first with the hsma_trsm rules (synthetic requests skip the pointer and
+ * leading-dimension checks), a request with m == 0 or n == 0 gives
+ * HSMA_INVALID_SIZE, a real request with alpha_im != 0 HSMA_INVALID_VALUE,
+ * one whose footprint exceeds the whole budget HSMA_TOO_LARGE, and a queue
+ * being destroyed HSMA_QUEUE_CLOSED.  Device-input requests must keep A and B
+ * alive and untouched until they complete.
+ */
+hsma_status hsma_queue_submit(hsma_queue *queue, const hsma_request *reqs, int64_t count,
+                              uint64_t *tickets);
+
+/* State of one request: HSMA_SUCCESS (done), HSMA_PENDING (queued or
+ * running), its failure status, or HSMA_NOT_FOUND (unknown or released).
+ * info may be NULL. */
+hsma_status hsma_queue_poll(hsma_queue *queue, uint64_t ticket, hsma_request_info *info);
+
+/* Block until the request finishes or timeout_ns passes (< 0: no limit):
+ * HSMA_SUCCESS, its failure status, HSMA_TIMEOUT or HSMA_NOT_FOUND. */
+hsma_status hsma_queue_wait(hsma_queue *queue, uint64_t ticket, int64_t timeout_ns,
+                            hsma_request_info *info);
+
+/* Forget a finished request and free what the server holds for it (a kept
+ * synthetic result).  Still running -> HSMA_PENDING, nothing done.  Records of
+ * finished requests stay until released. */
+hsma_status hsma_queue_release(hsma_queue *queue, uint64_t ticket);
+
+hsma_status hsma_queue_stats(hsma_queue *queue, hsma_queue_statistics *stats);
+
+/* Close the queue: later submits fail with HSMA_QUEUE_CLOSED, everything
+ * admissible still runs to completion, requests that can no longer be
+ * admitted (their budget is held by kept results) fail with
+ * HSMA_QUEUE_CLOSED; then the scheduler stops and all server memory is
+ * freed.  Waits for the device work the queue launched. */
+hsma_status hsma_queue_destroy(hsma_queue *queue);
+
 #ifdef __cplusplus
 }
 #endif

@@ -67,6 +67,40 @@ class PhaseStat(ctypes.Structure):
     _fields_ = [("launches", ctypes.c_int64), ("ms", ctypes.c_double), ("flops", ctypes.c_double)]
 
 
+class QueueConfig(ctypes.Structure):
+    _fields_ = [("backend", ctypes.c_int32), ("n_streams", ctypes.c_int32),
+                ("max_inflight", ctypes.c_int32), ("poll_us", ctypes.c_int32),
+                ("hbm_budget_bytes", ctypes.c_uint64), ("sim_flops_per_ns", ctypes.c_double),
+                ("sim_fixed_ns", ctypes.c_double)]
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("prob", Problem), ("input", ctypes.c_int32),
+                ("release_on_completion", ctypes.c_int32), ("key", ctypes.c_uint64),
+                ("t_arrival_ns", ctypes.c_double)]
+
+
+class RequestInfo(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("path", ctypes.c_int32),
+                ("t_arrival_ns", ctypes.c_double), ("t_admit_ns", ctypes.c_double),
+                ("t_done_ns", ctypes.c_double), ("A", ctypes.c_void_p), ("B", ctypes.c_void_p),
+                ("lda", ctypes.c_int64), ("ldb", ctypes.c_int64)]
+
+
+class QueueStatistics(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_int64), ("rejected", ctypes.c_int64),
+                ("completed", ctypes.c_int64), ("failed", ctypes.c_int64),
+                ("pending", ctypes.c_int64), ("inflight", ctypes.c_int64),
+                ("bytes_in_use", ctypes.c_uint64), ("bytes_peak", ctypes.c_uint64),
+                ("p50_ns", ctypes.c_double), ("p99_ns", ctypes.c_double),
+                ("max_ns", ctypes.c_double), ("mean_ns", ctypes.c_double),
+                ("solves_per_s", ctypes.c_double)]
+
+
+BACKEND_HIP, BACKEND_SIMULATED = 0, 1
+INPUT_DEVICE, INPUT_SYNTHETIC = 0, 1
+
+
 PHASE_DIAG_INV, PHASE_UPDATE, PHASE_LEAF, PHASE_SMALL, PHASE_OTHER = range(5)
 PHASE_COUNT = 5
 PHASE_NAMES = ["diag_inv", "update", "leaf_solve", "small", "other"]
@@ -110,6 +144,27 @@ def lib():
         L.hsma_profile_begin.restype = i32
         L.hsma_profile_end.argtypes = [ctypes.POINTER(PhaseStat), ctypes.c_int]
         L.hsma_profile_end.restype = i32
+        u64 = ctypes.c_uint64
+        L.hsma_generate_inputs.argtypes = [i32, i64, i64, u64, vp, vp, vp]
+        L.hsma_generate_inputs.restype = i32
+        L.hsma_request_footprint.argtypes = [ctypes.POINTER(Request), ctypes.POINTER(u64)]
+        L.hsma_request_footprint.restype = i32
+        L.hsma_clock_ns.argtypes = []
+        L.hsma_clock_ns.restype = ctypes.c_double
+        L.hsma_queue_create.argtypes = [ctypes.POINTER(QueueConfig), ctypes.POINTER(vp)]
+        L.hsma_queue_create.restype = i32
+        L.hsma_queue_submit.argtypes = [vp, ctypes.POINTER(Request), i64, ctypes.POINTER(u64)]
+        L.hsma_queue_submit.restype = i32
+        L.hsma_queue_poll.argtypes = [vp, u64, ctypes.POINTER(RequestInfo)]
+        L.hsma_queue_poll.restype = i32
+        L.hsma_queue_wait.argtypes = [vp, u64, i64, ctypes.POINTER(RequestInfo)]
+        L.hsma_queue_wait.restype = i32
+        L.hsma_queue_release.argtypes = [vp, u64]
+        L.hsma_queue_release.restype = i32
+        L.hsma_queue_stats.argtypes = [vp, ctypes.POINTER(QueueStatistics)]
+        L.hsma_queue_stats.restype = i32
+        L.hsma_queue_destroy.argtypes = [vp]
+        L.hsma_queue_destroy.restype = i32
         _lib = L
     return _lib
 
@@ -355,3 +410,143 @@ def lookup_block_size(complex_: bool, m: int, n: int) -> int:
 
 def version() -> str:
     return lib().hsma_version().decode()
+
+
+# ---------------------------------------------------------------------------
+# Synthetic inputs and the serving queue
+# ---------------------------------------------------------------------------
+
+def generate_inputs(m: int, n: int, key: int, complex_: bool = False, stream=None):
+    """L (m x m) and B (m x n), column-major with ld = m, drawn on the GPU from
+    Philox4x32-10 under ``key`` (the library's synthetic workload)."""
+    torch = _torch()
+    dt = torch.complex128 if complex_ else torch.float64
+    L = colmajor(m, m, dt)
+    B = colmajor(m, n, dt)
+    st = lib().hsma_generate_inputs(C64F if complex_ else R64F, m, n, key & (2**64 - 1),
+                                    ctypes.c_void_p(L.data_ptr()), ctypes.c_void_p(B.data_ptr()),
+                                    ctypes.c_void_p(_stream_handle(stream)))
+    _check(st, "hsma_generate_inputs")
+    return L, B
+
+
+def matrix_from_pointer(ptr: int, rows: int, cols: int, ld: int, complex_: bool = False) -> np.ndarray:
+    """Host copy (numpy, column-major) of a device matrix known only by its
+    address, such as a kept synthetic result of the queue."""
+    hip = ctypes.CDLL("libamdhip64.so.7")   # the runtime the library and torch share
+    hip.hipMemcpy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int]
+    hip.hipMemcpy.restype = ctypes.c_int
+    buf = np.empty((cols, ld), dtype=np.complex128 if complex_ else np.float64)
+    if buf.size:
+        st = hip.hipMemcpy(buf.ctypes.data, ptr, buf.nbytes, 2)   # device to host
+        if st != 0:
+            raise HsmaError(5, f"hipMemcpy failed ({st})")
+    return np.asfortranarray(buf[:, :rows].T)
+
+
+def clock_ns() -> float:
+    """The queue's monotonic clock (ns)."""
+    return lib().hsma_clock_ns()
+
+
+def request(m: int, n: int, alpha=1.0, unit: bool = False, complex_: bool = False,
+            key: Optional[int] = None, L=None, B=None, release_on_completion: bool = True,
+            t_arrival_ns: float = 0.0) -> Request:
+    """A queue request: synthetic (``key`` given; the server allocates and
+    fills L and B) or on caller tensors ``L``, ``B``."""
+    code = C64F if complex_ else R64F
+    a = complex(alpha)
+    if code == R64F and a.imag != 0:
+        raise ValueError("complex alpha for a real problem")
+    if key is not None:
+        prob = Problem(UNIT if unit else NON_UNIT, code, m, n, a.real, a.imag, None, max(1, m),
+                       None, max(1, m))
+        return Request(prob, INPUT_SYNTHETIC, 1 if release_on_completion else 0,
+                       key & (2**64 - 1), t_arrival_ns)
+    prob = problem_struct(L, B, alpha, unit)
+    return Request(prob, INPUT_DEVICE, 0, 0, t_arrival_ns)
+
+
+def request_footprint(req: Request) -> int:
+    """Bytes of HBM budget the queue reserves for ``req``."""
+    b = ctypes.c_uint64()
+    _check(lib().hsma_request_footprint(ctypes.byref(req), ctypes.byref(b)), "hsma_request_footprint")
+    return int(b.value)
+
+
+class Queue:
+    """Continuous-batching request queue (``hsma_queue_*``).
+
+    ``Queue(simulated=True, ...)`` runs the same scheduler with modelled
+    device time and no GPU work (for policy tests)."""
+
+    def __init__(self, simulated: bool = False, n_streams: int = 0, max_inflight: int = 0,
+                 poll_us: int = 0, hbm_budget_bytes: int = 0, sim_flops_per_ns: float = 0.0,
+                 sim_fixed_ns: float = 0.0):
+        cfg = QueueConfig(BACKEND_SIMULATED if simulated else BACKEND_HIP, n_streams,
+                          max_inflight, poll_us, hbm_budget_bytes, sim_flops_per_ns, sim_fixed_ns)
+        h = ctypes.c_void_p()
+        _check(lib().hsma_queue_create(ctypes.byref(cfg), ctypes.byref(h)), "hsma_queue_create")
+        self._h = h
+        self._keep = {}   # caller tensors of device-input requests, kept alive
+
+    def submit(self, reqs, tensors=None):
+        """Submit Request structs (one or a list); returns the tickets.  Pass
+        the tensors a device-input request uses in ``tensors`` to keep them
+        alive until it is released."""
+        single = isinstance(reqs, Request)
+        reqs = [reqs] if single else list(reqs)
+        arr = (Request * max(1, len(reqs)))(*reqs)
+        tk = (ctypes.c_uint64 * max(1, len(reqs)))()
+        _check(lib().hsma_queue_submit(self._h, arr, len(reqs), tk), "hsma_queue_submit")
+        out = [int(tk[i]) for i in range(len(reqs))]
+        if tensors is not None:
+            for t, ts in zip(out, [tensors] if single else tensors):
+                self._keep[t] = ts
+        return out[0] if single else out
+
+    @staticmethod
+    def _info(info: RequestInfo) -> dict:
+        return {"status": info.status, "path": info.path, "t_arrival_ns": info.t_arrival_ns,
+                "t_admit_ns": info.t_admit_ns, "t_done_ns": info.t_done_ns,
+                "A": info.A, "B": info.B, "lda": info.lda, "ldb": info.ldb}
+
+    def poll(self, ticket: int):
+        """(status code, info dict)."""
+        info = RequestInfo()
+        st = lib().hsma_queue_poll(self._h, ticket, ctypes.byref(info))
+        return st, self._info(info)
+
+    def wait(self, ticket: int, timeout_s: Optional[float] = None) -> dict:
+        info = RequestInfo()
+        t = -1 if timeout_s is None else int(timeout_s * 1e9)
+        st = lib().hsma_queue_wait(self._h, ticket, t, ctypes.byref(info))
+        _check(st, f"hsma_queue_wait({ticket})")
+        return self._info(info)
+
+    def release(self, ticket: int) -> None:
+        _check(lib().hsma_queue_release(self._h, ticket), f"hsma_queue_release({ticket})")
+        self._keep.pop(ticket, None)
+
+    def stats(self) -> dict:
+        s = QueueStatistics()
+        _check(lib().hsma_queue_stats(self._h, ctypes.byref(s)), "hsma_queue_stats")
+        return {f[0]: getattr(s, f[0]) for f in QueueStatistics._fields_}
+
+    def close(self) -> None:
+        if self._h:
+            _check(lib().hsma_queue_destroy(self._h), "hsma_queue_destroy")
+            self._h = None
+            self._keep.clear()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

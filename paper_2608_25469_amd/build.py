@@ -32,8 +32,16 @@ COMMON = [
 ]
 
 
-def _compile(src: str) -> str:
+def _headers_mtime() -> float:
+    hs = glob.glob(os.path.join(CSRC, "*.h")) + glob.glob(os.path.join(HERE, "..", "include", "*.h"))
+    return max([os.path.getmtime(h) for h in hs] + [os.path.getmtime(__file__)])
+
+
+def _compile(src: str, incremental: bool = False) -> str:
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
+    if incremental and os.path.exists(obj) and \
+            os.path.getmtime(obj) > max(os.path.getmtime(src), _headers_mtime()):
+        return f"{os.path.basename(src)} up to date"
     # .cpp files hold host-only code but use the HIP runtime API; they are
     # compiled as HIP so the same toolchain and headers apply.
     cmd = [HIPCC, *COMMON, "-x", "hip", "-c", src, "-o", obj]
@@ -44,12 +52,14 @@ def _compile(src: str) -> str:
     return f"{os.path.basename(src)} {time.time() - t0:.1f}s"
 
 
-def build(verbose: bool = True, jobs: int | None = None) -> str:
+def build(verbose: bool = True, jobs: int | None = None, incremental: bool = False) -> str:
+    """Compile every source (``incremental``: only those older than their
+    object file and every header are skipped) and link the library."""
     os.makedirs(BUILD, exist_ok=True)
     srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")) + glob.glob(os.path.join(CSRC, "*.cpp")))
     jobs = jobs or min(len(srcs), max(1, (os.cpu_count() or 4)))
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
-        for msg in ex.map(_compile, srcs):
+        for msg in ex.map(lambda src: _compile(src, incremental), srcs):
             if verbose:
                 print("  built", msg, flush=True)
     objs = [os.path.join(BUILD, os.path.basename(s) + ".o") for s in srcs]
@@ -71,5 +81,5 @@ def clean() -> None:
 
 if __name__ == "__main__":
     t = time.time()
-    build()
+    build(incremental="--incremental" in sys.argv)
     print(f"done in {time.time() - t:.1f}s", file=sys.stderr)

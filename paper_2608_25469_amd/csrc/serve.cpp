@@ -1,0 +1,558 @@
+// Request queue with continuous batching (the paper's outlook on batched
+// TRSM, Sec. 6, carried to a serving loop).
+//
+// Clients submit requests at any time; a scheduler thread
+//   1. retires finished work (event polling), releasing its HBM budget and
+//      recording its latency,
+//   2. admits pending requests in arrival order while the HBM budget and the
+//      in-flight limit allow (a request larger than the whole budget is
+//      rejected at submit, so the head of the queue always fits once the
+//      work ahead of it retires),
+//   3. launches what it admitted: all small requests (m <= 64) of the round
+//      as one batched call, every larger request as its own blocked solve on
+//      one of several streams,
+// so requests arriving while others run reach the device as soon as slots
+// and memory free up, and their work overlaps on the GPU.
+//
+// Requests either bring device pointers (the caller keeps them alive until
+// completion) or ask the server to allocate and fill L and B from a Philox
+// key (synthetic load).  A simulation backend runs the same policy with
+// modelled completion times so the scheduler can be tested without a GPU.
+
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "internal.h"
+
+namespace hsma {
+
+size_t blocked_workspace_bytes(bool cx, int64_t m, int ib);
+int lookup_block_size(bool cx, int64_t m, int64_t n);
+hsma_status validate(int diag, int dtype, int64_t m, int64_t n, const void *alpha, const void *A,
+                     int64_t lda, const void *B, int64_t ldb, bool *quick);
+hsma_status launch_gen_inputs(bool cx, int64_t m, int64_t n, uint64_t key, double *L, double *B,
+                              hipStream_t s);
+
+namespace {
+
+double clock_ns() {
+    return (double)std::chrono::duration_cast<std::chrono::nanoseconds>(
+               std::chrono::steady_clock::now().time_since_epoch())
+        .count();
+}
+
+enum State { PENDING = 0, RUNNING = 1, DONE = 2, FAILED = 3 };
+
+constexpr size_t kSmallShare = 4096;  // descriptor share of a small request
+
+size_t data_bytes(const hsma_problem &p) {
+    const size_t es = p.dtype == HSMA_C64F ? 16 : 8;
+    return es * (size_t)(p.m * p.m + p.m * p.n);
+}
+
+size_t footprint(const hsma_request &r) {
+    const hsma_problem &p = r.prob;
+    const bool cx = p.dtype == HSMA_C64F;
+    size_t f = r.input == HSMA_INPUT_SYNTHETIC ? data_bytes(p) : 0;
+    f += p.m > 64 ? blocked_workspace_bytes(cx, p.m, lookup_block_size(cx, p.m, p.n)) : kSmallShare;
+    return f;
+}
+
+struct Req {
+    uint64_t ticket = 0;
+    hsma_request r{};
+    double t_arrival = 0, t_admit = 0, t_done = 0;
+    size_t held = 0;          // budget this request holds now
+    void *mem = nullptr;      // server allocation (synthetic inputs)
+    hipStream_t mem_stream = nullptr;
+    const double *A = nullptr;
+    double *B = nullptr;
+    int64_t lda = 0, ldb = 0;
+    State state = PENDING;
+    hsma_status status = HSMA_SUCCESS;
+    int path = 0;
+};
+
+struct Inflight {
+    hipEvent_t ev = nullptr;  // HIP backend
+    double t_model_done = 0;  // simulation backend
+    std::vector<Req *> reqs;
+};
+
+}  // namespace
+}  // namespace hsma
+
+struct hsma_queue {
+    hsma_queue_config cfg{};
+    std::mutex mu;
+    std::condition_variable cv_sched, cv_done;
+    std::deque<hsma::Req *> pending;
+    std::unordered_map<uint64_t, hsma::Req *> all;
+    std::vector<hsma::Inflight> inflight;
+    uint64_t next_ticket = 1;
+    size_t budget_used = 0, budget_peak = 0;
+    int64_t n_inflight = 0;
+    bool closing = false, stopped = false;
+    std::thread sched;
+    int device = 0;
+    hipStream_t small_stream = nullptr;
+    std::vector<hipStream_t> streams;
+    size_t rr = 0;
+    std::vector<double> sim_free_at;  // simulation: per-stream busy-until (last = small)
+    // statistics
+    std::vector<double> latencies_ns;
+    int64_t submitted = 0, rejected = 0, completed = 0, failed = 0;
+    double t_first_submit = 0, t_last_done = 0;
+};
+
+namespace hsma {
+namespace {
+
+void free_mem(Req *r) {
+    if (r->mem) {
+        (void)ws_free(r->mem, r->mem_stream);
+        r->mem = nullptr;
+    }
+}
+
+// Called with the lock held.
+void finish(hsma_queue *q, Req *r, double t, hsma_status st) {
+    r->t_done = t;
+    r->state = st == HSMA_SUCCESS ? DONE : FAILED;
+    r->status = st;
+    q->n_inflight--;
+    if (st == HSMA_SUCCESS) {
+        q->completed++;
+        q->latencies_ns.push_back(t - r->t_arrival);
+    } else {
+        q->failed++;
+    }
+    q->t_last_done = std::max(q->t_last_done, t);
+    const bool keep = st == HSMA_SUCCESS && r->r.input == HSMA_INPUT_SYNTHETIC &&
+                      !r->r.release_on_completion;
+    const size_t keep_bytes = keep ? data_bytes(r->r.prob) : 0;
+    if (!keep) free_mem(r);
+    q->budget_used -= r->held - keep_bytes;
+    r->held = keep_bytes;
+}
+
+// Enqueue the admitted requests (HIP backend).  Called without the lock.
+void launch_admitted(hsma_queue *q, std::vector<Req *> &adm) {
+    std::vector<Req *> small;
+    std::vector<hsma_problem> small_probs;
+    for (Req *r : adm) {
+        const hsma_problem &p = r->r.prob;
+        const bool cx = p.dtype == HSMA_C64F;
+        hipStream_t s = p.m <= 64 ? q->small_stream : q->streams[q->rr++ % q->streams.size()];
+        hsma_status st = HSMA_SUCCESS;
+        if (r->r.input == HSMA_INPUT_SYNTHETIC) {
+            st = ws_alloc(&r->mem, data_bytes(p), s);
+            if (st == HSMA_SUCCESS) {
+                r->mem_stream = s;
+                r->A = static_cast<double *>(r->mem);
+                r->B = static_cast<double *>(r->mem) + (cx ? 2 : 1) * p.m * p.m;
+                r->lda = r->ldb = p.m;
+                st = launch_gen_inputs(cx, p.m, p.n, r->r.key, const_cast<double *>(r->A), r->B, s);
+            } else {
+                r->mem = nullptr;
+            }
+        } else {
+            r->A = static_cast<const double *>(p.A);
+            r->B = static_cast<double *>(p.B);
+            r->lda = p.lda;
+            r->ldb = p.ldb;
+        }
+        if (st != HSMA_SUCCESS) {
+            std::lock_guard<std::mutex> lk(q->mu);
+            finish(q, r, clock_ns(), st);
+            continue;
+        }
+        if (p.m <= 64) {
+            hsma_problem sp = p;
+            sp.A = r->A;
+            sp.B = r->B;
+            sp.lda = r->lda;
+            sp.ldb = r->ldb;
+            small_probs.push_back(sp);
+            small.push_back(r);
+            r->path = 1;
+            continue;
+        }
+        const double al[2] = {p.alpha_re, p.alpha_im};
+        r->path = 2;
+        st = hsma_trsm((hsma_diag)p.diag, p.m, p.n, al, r->A, r->lda, r->B, r->ldb,
+                       (hsma_dtype)p.dtype, s);
+        Inflight f;
+        f.reqs.push_back(r);
+        if (st == HSMA_SUCCESS) {
+            hipError_t e = hipEventCreateWithFlags(&f.ev, hipEventDisableTiming);
+            if (e == hipSuccess) e = hipEventRecord(f.ev, s);
+            if (e != hipSuccess) st = hip_fail(e);
+        }
+        if (st != HSMA_SUCCESS) (void)hipStreamSynchronize(s);  // generator may still use r->mem
+        std::lock_guard<std::mutex> lk(q->mu);
+        if (st == HSMA_SUCCESS) {
+            q->inflight.push_back(f);
+        } else {
+            if (f.ev) (void)hipEventDestroy(f.ev);
+            finish(q, r, clock_ns(), st);
+        }
+    }
+    if (small.empty()) return;
+    hsma_status st = hsma_trsm_batched(small_probs.data(), (int64_t)small_probs.size(), nullptr,
+                                       q->small_stream);
+    Inflight f;
+    f.reqs = small;
+    if (st == HSMA_SUCCESS) {
+        hipError_t e = hipEventCreateWithFlags(&f.ev, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventRecord(f.ev, q->small_stream);
+        if (e != hipSuccess) st = hip_fail(e);
+    }
+    if (st != HSMA_SUCCESS) (void)hipStreamSynchronize(q->small_stream);
+    std::lock_guard<std::mutex> lk(q->mu);
+    if (st == HSMA_SUCCESS) {
+        q->inflight.push_back(f);
+    } else {
+        if (f.ev) (void)hipEventDestroy(f.ev);
+        for (Req *r : small) finish(q, r, clock_ns(), st);
+    }
+}
+
+// Simulation backend: streams run their launches one after another; a launch
+// takes sim_fixed_ns + flops / sim_flops_per_ns.  The small requests of one
+// round form one launch on the small stream lasting as long as its largest.
+void launch_simulated(hsma_queue *q, std::vector<Req *> &adm) {
+    const double now = clock_ns();
+    std::lock_guard<std::mutex> lk(q->mu);
+    const size_t n_big = (size_t)q->cfg.n_streams;
+    double small_ns = 0;
+    Inflight sm;
+    for (Req *r : adm) {
+        const hsma_problem &p = r->r.prob;
+        const double fl = (double)p.m * p.m * p.n * (p.dtype == HSMA_C64F ? 4.0 : 1.0);
+        const double dur = q->cfg.sim_fixed_ns + fl / q->cfg.sim_flops_per_ns;
+        if (p.m <= 64) {
+            small_ns = std::max(small_ns, dur);
+            sm.reqs.push_back(r);
+            r->path = 1;
+        } else {
+            double &free_at = q->sim_free_at[q->rr++ % n_big];
+            free_at = std::max(free_at, now) + dur;
+            Inflight f;
+            f.t_model_done = free_at;
+            f.reqs.push_back(r);
+            r->path = 2;
+            q->inflight.push_back(f);
+        }
+    }
+    if (!sm.reqs.empty()) {
+        double &free_at = q->sim_free_at[n_big];
+        free_at = std::max(free_at, now) + small_ns;
+        sm.t_model_done = free_at;
+        q->inflight.push_back(sm);
+    }
+}
+
+void scheduler(hsma_queue *q) {
+    const bool hip = q->cfg.backend == HSMA_BACKEND_HIP;
+    if (hip) (void)hipSetDevice(q->device);
+    std::unique_lock<std::mutex> lk(q->mu);
+    for (;;) {
+        // 1. completions
+        const double t = clock_ns();
+        bool retired = false;
+        for (size_t i = 0; i < q->inflight.size();) {
+            Inflight &f = q->inflight[i];
+            bool done = false;
+            hsma_status st = HSMA_SUCCESS;
+            if (hip) {
+                const hipError_t e = hipEventQuery(f.ev);
+                if (e == hipSuccess) {
+                    done = true;
+                } else if (e != hipErrorNotReady) {
+                    done = true;
+                    st = hip_fail(e);
+                }
+            } else {
+                done = t >= f.t_model_done;
+            }
+            if (done) {
+                for (Req *r : f.reqs) finish(q, r, t, st);
+                if (f.ev) (void)hipEventDestroy(f.ev);
+                f = q->inflight.back();
+                q->inflight.pop_back();
+                retired = true;
+            } else {
+                ++i;
+            }
+        }
+        if (retired) q->cv_done.notify_all();
+        // 2. admission, strictly in arrival order
+        std::vector<Req *> adm;
+        while (!q->pending.empty() && q->n_inflight < q->cfg.max_inflight) {
+            Req *r = q->pending.front();
+            const size_t f = footprint(r->r);
+            if (q->budget_used + f > q->cfg.hbm_budget_bytes) break;
+            q->pending.pop_front();
+            q->budget_used += f;
+            r->held = f;
+            q->budget_peak = std::max(q->budget_peak, q->budget_used);
+            q->n_inflight++;
+            r->state = RUNNING;
+            r->t_admit = t;
+            adm.push_back(r);
+        }
+        if (!adm.empty()) {
+            lk.unlock();
+            if (hip) launch_admitted(q, adm);
+            else launch_simulated(q, adm);
+            lk.lock();
+            continue;
+        }
+        if (q->closing && q->inflight.empty()) {
+            // What is still pending can never be admitted: its budget is held
+            // by kept results, and nobody will release them any more.
+            while (!q->pending.empty()) {
+                Req *r = q->pending.front();
+                q->pending.pop_front();
+                q->n_inflight++;  // finish() retires one in-flight request
+                finish(q, r, t, HSMA_QUEUE_CLOSED);
+            }
+            break;
+        }
+        // 3. nothing to launch: wait for arrivals or releases, or poll
+        if (q->inflight.empty())
+            q->cv_sched.wait_for(lk, std::chrono::milliseconds(5));
+        else
+            q->cv_sched.wait_for(lk, std::chrono::microseconds(q->cfg.poll_us));
+    }
+    q->stopped = true;
+    q->cv_done.notify_all();
+}
+
+void fill_info(const Req *r, hsma_request_info *info) {
+    if (!info) return;
+    std::memset(info, 0, sizeof(*info));
+    info->status = r->state == DONE ? HSMA_SUCCESS : r->state == FAILED ? r->status : HSMA_PENDING;
+    info->path = r->path;
+    info->t_arrival_ns = r->t_arrival;
+    info->t_admit_ns = r->t_admit;
+    info->t_done_ns = r->t_done;
+    info->A = r->A;
+    info->B = r->B;
+    info->lda = r->lda;
+    info->ldb = r->ldb;
+}
+
+hsma_status state_status(const Req *r) {
+    return r->state == DONE ? HSMA_SUCCESS : r->state == FAILED ? r->status : HSMA_PENDING;
+}
+
+}  // namespace
+}  // namespace hsma
+
+extern "C" {
+
+double hsma_clock_ns(void) { return hsma::clock_ns(); }
+
+hsma_status hsma_request_footprint(const hsma_request *req, uint64_t *bytes) {
+    if (!req || !bytes) return HSMA_INVALID_POINTER;
+    if (req->prob.dtype != HSMA_R64F && req->prob.dtype != HSMA_C64F) return HSMA_INVALID_VALUE;
+    if (req->prob.m < 0 || req->prob.n < 0) return HSMA_INVALID_SIZE;
+    *bytes = hsma::footprint(*req);
+    return HSMA_SUCCESS;
+}
+
+hsma_status hsma_queue_create(const hsma_queue_config *cfg, hsma_queue **out) {
+    using namespace hsma;
+    if (!out) return HSMA_INVALID_POINTER;
+    *out = nullptr;
+    hsma_queue_config c{};
+    if (cfg) c = *cfg;
+    if (c.backend != HSMA_BACKEND_HIP && c.backend != HSMA_BACKEND_SIMULATED)
+        return HSMA_INVALID_VALUE;
+    if (c.max_inflight < 0 || c.n_streams < 0 || c.poll_us < 0 || c.sim_fixed_ns < 0)
+        return HSMA_INVALID_VALUE;
+    if (c.hbm_budget_bytes == 0) c.hbm_budget_bytes = (uint64_t)32 << 30;
+    if (c.max_inflight == 0) c.max_inflight = 1024;
+    if (c.n_streams == 0) c.n_streams = 4;
+    if (c.poll_us == 0) c.poll_us = 20;
+    if (!(c.sim_flops_per_ns > 0)) c.sim_flops_per_ns = 40000.0;
+    hsma_queue *q = new hsma_queue();
+    q->cfg = c;
+    if (c.backend == HSMA_BACKEND_HIP) {
+        hipError_t e = hipGetDevice(&q->device);
+        if (e == hipSuccess) e = hipStreamCreateWithFlags(&q->small_stream, hipStreamNonBlocking);
+        for (int i = 0; e == hipSuccess && i < c.n_streams; ++i) {
+            hipStream_t s;
+            e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+            if (e == hipSuccess) q->streams.push_back(s);
+        }
+        if (e != hipSuccess) {
+            for (auto s : q->streams) (void)hipStreamDestroy(s);
+            if (q->small_stream) (void)hipStreamDestroy(q->small_stream);
+            delete q;
+            return hip_fail(e);
+        }
+    } else {
+        q->sim_free_at.assign((size_t)c.n_streams + 1, 0.0);
+    }
+    q->sched = std::thread(scheduler, q);
+    *out = q;
+    return HSMA_SUCCESS;
+}
+
+hsma_status hsma_queue_submit(hsma_queue *q, const hsma_request *reqs, int64_t count,
+                              uint64_t *tickets) {
+    using namespace hsma;
+    if (!q) return HSMA_INVALID_POINTER;
+    if (count < 0) return HSMA_INVALID_SIZE;
+    if (count > 0 && (!reqs || !tickets)) return HSMA_INVALID_POINTER;
+    for (int64_t i = 0; i < count; ++i) {
+        const hsma_request &r = reqs[i];
+        const hsma_problem &p = r.prob;
+        if (r.input != HSMA_INPUT_DEVICE && r.input != HSMA_INPUT_SYNTHETIC)
+            return HSMA_INVALID_VALUE;
+        if (r.release_on_completion != 0 && r.release_on_completion != 1)
+            return HSMA_INVALID_VALUE;
+        const bool syn = r.input == HSMA_INPUT_SYNTHETIC;
+        const double al[2] = {p.alpha_re, p.alpha_im};
+        static const double dummy = 0.0;
+        bool quick = false;
+        const int64_t ld_syn = p.m > 1 ? p.m : 1;
+        const hsma_status st =
+            validate(p.diag, p.dtype, p.m, p.n, al, syn ? &dummy : p.A, syn ? ld_syn : p.lda,
+                     syn ? &dummy : p.B, syn ? ld_syn : p.ldb, &quick);
+        if (st != HSMA_SUCCESS) return st;
+        if (quick) return HSMA_INVALID_SIZE;
+        if (p.dtype == HSMA_R64F && p.alpha_im != 0.0) return HSMA_INVALID_VALUE;
+        if (footprint(r) > q->cfg.hbm_budget_bytes) {
+            std::lock_guard<std::mutex> lk(q->mu);
+            q->rejected++;
+            return HSMA_TOO_LARGE;
+        }
+    }
+    {
+        std::lock_guard<std::mutex> lk(q->mu);
+        if (q->closing) return HSMA_QUEUE_CLOSED;
+        const double t = clock_ns();
+        for (int64_t i = 0; i < count; ++i) {
+            Req *r = new Req();
+            r->ticket = q->next_ticket++;
+            r->r = reqs[i];
+            r->t_arrival = reqs[i].t_arrival_ns > 0 ? reqs[i].t_arrival_ns : t;
+            q->all[r->ticket] = r;
+            q->pending.push_back(r);
+            tickets[i] = r->ticket;
+            if (q->submitted == 0) q->t_first_submit = std::min(t, r->t_arrival);
+            q->submitted++;
+        }
+    }
+    q->cv_sched.notify_one();
+    return HSMA_SUCCESS;
+}
+
+hsma_status hsma_queue_poll(hsma_queue *q, uint64_t ticket, hsma_request_info *info) {
+    if (!q) return HSMA_INVALID_POINTER;
+    std::lock_guard<std::mutex> lk(q->mu);
+    auto it = q->all.find(ticket);
+    if (it == q->all.end()) return HSMA_NOT_FOUND;
+    hsma::fill_info(it->second, info);
+    return hsma::state_status(it->second);
+}
+
+hsma_status hsma_queue_wait(hsma_queue *q, uint64_t ticket, int64_t timeout_ns,
+                            hsma_request_info *info) {
+    if (!q) return HSMA_INVALID_POINTER;
+    std::unique_lock<std::mutex> lk(q->mu);
+    const auto deadline = std::chrono::steady_clock::now() +
+                          std::chrono::nanoseconds(timeout_ns < 0 ? (int64_t)1 << 62 : timeout_ns);
+    for (;;) {
+        auto it = q->all.find(ticket);
+        if (it == q->all.end()) return HSMA_NOT_FOUND;
+        const hsma::Req *r = it->second;
+        if (r->state == hsma::DONE || r->state == hsma::FAILED) {
+            hsma::fill_info(r, info);
+            return hsma::state_status(r);
+        }
+        if (q->stopped) return HSMA_QUEUE_CLOSED;
+        if (q->cv_done.wait_until(lk, deadline) == std::cv_status::timeout) {
+            hsma::fill_info(r, info);
+            return HSMA_TIMEOUT;
+        }
+    }
+}
+
+hsma_status hsma_queue_release(hsma_queue *q, uint64_t ticket) {
+    if (!q) return HSMA_INVALID_POINTER;
+    {
+        std::lock_guard<std::mutex> lk(q->mu);
+        auto it = q->all.find(ticket);
+        if (it == q->all.end()) return HSMA_NOT_FOUND;
+        hsma::Req *r = it->second;
+        if (r->state != hsma::DONE && r->state != hsma::FAILED) return HSMA_PENDING;
+        hsma::free_mem(r);
+        q->budget_used -= r->held;
+        q->all.erase(it);
+        delete r;
+    }
+    q->cv_sched.notify_one();
+    return HSMA_SUCCESS;
+}
+
+hsma_status hsma_queue_stats(hsma_queue *q, hsma_queue_statistics *st) {
+    if (!q || !st) return HSMA_INVALID_POINTER;
+    std::lock_guard<std::mutex> lk(q->mu);
+    std::memset(st, 0, sizeof(*st));
+    st->submitted = q->submitted;
+    st->rejected = q->rejected;
+    st->completed = q->completed;
+    st->failed = q->failed;
+    st->pending = (int64_t)q->pending.size();
+    st->inflight = q->n_inflight;
+    st->bytes_in_use = q->budget_used;
+    st->bytes_peak = q->budget_peak;
+    if (!q->latencies_ns.empty()) {
+        std::vector<double> v = q->latencies_ns;
+        std::sort(v.begin(), v.end());
+        auto pct = [&](double p) { return v[(size_t)(p * (double)(v.size() - 1) + 0.5)]; };
+        st->p50_ns = pct(0.50);
+        st->p99_ns = pct(0.99);
+        st->max_ns = v.back();
+        double sum = 0;
+        for (double x : v) sum += x;
+        st->mean_ns = sum / (double)v.size();
+        const double span = q->t_last_done - q->t_first_submit;
+        st->solves_per_s = span > 0 ? (double)q->completed / (span * 1e-9) : 0.0;
+    }
+    return HSMA_SUCCESS;
+}
+
+hsma_status hsma_queue_destroy(hsma_queue *q) {
+    if (!q) return HSMA_SUCCESS;
+    {
+        std::lock_guard<std::mutex> lk(q->mu);
+        q->closing = true;
+    }
+    q->cv_sched.notify_one();
+    if (q->sched.joinable()) q->sched.join();
+    for (auto &kv : q->all) {
+        hsma::free_mem(kv.second);
+        delete kv.second;
+    }
+    for (auto s : q->streams) (void)hipStreamSynchronize(s);
+    if (q->small_stream) (void)hipStreamSynchronize(q->small_stream);
+    for (auto s : q->streams) (void)hipStreamDestroy(s);
+    if (q->small_stream) (void)hipStreamDestroy(q->small_stream);
+    delete q;
+    return HSMA_SUCCESS;
+}
+
+}  // extern "C"

@@ -127,3 +127,56 @@ def test_batched_validation_without_device(lib):
     assert lib.hsma_trsm_batched(None, 3, None, None) == 3
     assert lib.hsma_trsm_batched(None, -1, None, None) == 2
     assert lib.hsma_trsm_batched(None, 0, None, None) == 0
+
+
+STRUCTS = {
+    "hsma_trsm_options": hs.TrsmOptions,
+    "hsma_trsm_report": hs.TrsmReport,
+    "hsma_problem": hs.Problem,
+    "hsma_phase_stat": hs.PhaseStat,
+    "hsma_queue_config": hs.QueueConfig,
+    "hsma_request": hs.Request,
+    "hsma_request_info": hs.RequestInfo,
+    "hsma_queue_statistics": hs.QueueStatistics,
+}
+
+
+def test_binding_structs_match_header(tmp_path):
+    """Size and every field offset of the ctypes mirrors equal the C
+    compiler's layout of the header's structs."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no host C compiler")
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "hsma.h"', "int main(void) {"]
+    for cname, py in STRUCTS.items():
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f in py._fields_:
+            lines.append(f'printf("{cname} {f[0]} %zu\\n", offsetof({cname}, {f[0]}));')
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                   check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {}
+    for ln in out:
+        if ln:
+            a, b, c = ln.split()
+            got[(a, b)] = int(c)
+    for cname, py in STRUCTS.items():
+        assert got[(cname, "size")] == ctypes.sizeof(py), cname
+        for f in py._fields_:
+            assert got[(cname, f[0])] == getattr(py, f[0]).offset, (cname, f[0])
+
+
+def test_generate_inputs_validation(lib):
+    g = lib.hsma_generate_inputs
+    assert g(3, 4, 4, 1, ctypes.c_void_p(16), ctypes.c_void_p(32), None) == 1
+    assert g(0, -1, 4, 1, ctypes.c_void_p(16), ctypes.c_void_p(32), None) == 2
+    assert g(0, 4, -1, 1, ctypes.c_void_p(16), ctypes.c_void_p(32), None) == 2
+    assert g(0, 0, 4, 1, None, None, None) == 0
+    assert g(0, 4, 4, 1, None, ctypes.c_void_p(32), None) == 3
+    assert g(1, 4, 4, 1, ctypes.c_void_p(16), None, None) == 3

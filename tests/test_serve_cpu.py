@@ -1,0 +1,242 @@
+"""Serving-queue policy on the simulation backend (no GPU).
+
+The simulation backend runs the library's own scheduler thread -- admission,
+grouping, stream assignment, completion, accounting -- with modelled launch
+durations instead of device work, so these tests exercise the same code the
+HIP backend uses, minus the launches.  Device-input requests carry fake,
+never-dereferenced pointers here.
+"""
+import ctypes
+import threading
+import time
+
+import numpy as np
+import pytest
+
+import paper_2608_25469_amd as hs
+
+pytestmark = pytest.mark.skipif(not hs.os.path.exists(hs.LIB_PATH), reason="library not built")
+
+FAKE = 0x1000  # never dereferenced by the simulation backend
+MS = 1e6       # ns
+
+
+def dev_req(m, n, cx=False, alpha=1.0, t_arrival_ns=0.0):
+    a = complex(alpha)
+    prob = hs.Problem(hs.NON_UNIT, hs.C64F if cx else hs.R64F, m, n, a.real, a.imag,
+                      ctypes.c_void_p(FAKE), m, ctypes.c_void_p(FAKE), m)
+    return hs.Request(prob, hs.INPUT_DEVICE, 0, 0, t_arrival_ns)
+
+
+def syn_req(m, n, key=1, cx=False, keep=False):
+    return hs.request(m, n, 1.0, complex_=cx, key=key, release_on_completion=not keep)
+
+
+def sim_queue(rate_flops_per_ns=1000.0, fixed_ns=0.0, **kw):
+    return hs.Queue(simulated=True, sim_flops_per_ns=rate_flops_per_ns, sim_fixed_ns=fixed_ns, **kw)
+
+
+def wait_all(q, tickets, timeout_s=20.0):
+    return [q.wait(t, timeout_s) for t in tickets]
+
+
+def test_fifo_admission_under_budget():
+    r = dev_req(1024, 1024)               # 1.07e9 flops -> ~1.1 ms at 1 TF/s... scaled below
+    fp = hs.request_footprint(r)
+    assert fp > 0
+    # budget for exactly one request at a time
+    with sim_queue(rate_flops_per_ns=200.0, hbm_budget_bytes=int(fp * 1.5)) as q:
+        tk = q.submit([dev_req(1024, 1024) for _ in range(5)])
+        infos = wait_all(q, tk)
+        st = q.stats()
+    assert [i["status"] for i in infos] == [0] * 5
+    assert all(i["path"] == 2 for i in infos)
+    admits = [i["t_admit_ns"] for i in infos]
+    dones = [i["t_done_ns"] for i in infos]
+    assert admits == sorted(admits)                # arrival order
+    for k in range(1, 5):                          # one at a time
+        assert admits[k] >= dones[k - 1]
+    assert st["bytes_peak"] <= int(fp * 1.5)
+    assert st["bytes_peak"] == fp
+    assert st["completed"] == 5 and st["failed"] == 0 and st["bytes_in_use"] == 0
+
+
+def test_too_large_rejected_all_or_nothing():
+    big = dev_req(4096, 512)
+    fp = hs.request_footprint(big)
+    with sim_queue(hbm_budget_bytes=fp - 1) as q:
+        with pytest.raises(hs.HsmaError) as e:
+            q.submit(big)
+        assert e.value.status == 7
+        with pytest.raises(hs.HsmaError) as e:
+            q.submit([dev_req(32, 32), big])       # nothing of this batch is queued
+        assert e.value.status == 7
+        st = q.stats()
+        assert st["rejected"] == 2 and st["submitted"] == 0
+        t = q.submit(dev_req(32, 32))
+        q.wait(t, 10)
+        assert q.stats()["submitted"] == 1
+
+
+def test_max_inflight_limit():
+    with sim_queue(rate_flops_per_ns=400.0, max_inflight=2, n_streams=8) as q:
+        tk = q.submit([dev_req(1024, 1024) for _ in range(6)])
+        infos = wait_all(q, tk)
+    iv = [(i["t_admit_ns"], i["t_done_ns"]) for i in infos]
+    for a, _ in iv:
+        live = sum(1 for s, e in iv if s <= a < e)
+        assert live <= 2
+
+
+def test_small_requests_grouped_per_round():
+    with sim_queue(rate_flops_per_ns=1.0) as q:
+        # one large request first keeps the scheduler busy while the small ones queue up
+        tk = q.submit([dev_req(16 + i % 48, 1 + i % 64, cx=bool(i % 3 == 0)) for i in range(50)])
+        infos = wait_all(q, tk)
+    assert all(i["path"] == 1 for i in infos)
+    assert len({i["t_admit_ns"] for i in infos}) == 1      # admitted in one round
+    assert len({i["t_done_ns"] for i in infos}) == 1       # one launch
+
+
+def test_kept_results_hold_budget_until_release():
+    r = syn_req(512, 256, keep=True)
+    fp = hs.request_footprint(r)
+    data = 8 * (512 * 512 + 512 * 256)
+    assert fp > data
+    with sim_queue(hbm_budget_bytes=int(fp * 1.5)) as q:
+        t1, t2 = q.submit([syn_req(512, 256, key=1, keep=True), syn_req(512, 256, key=2, keep=True)])
+        i1 = q.wait(t1, 10)
+        assert i1["status"] == 0
+        assert q.stats()["bytes_in_use"] == data           # result kept, workspace returned
+        time.sleep(0.05)
+        st, _ = q.poll(t2)
+        assert st == 9                                     # still pending: no room
+        assert q.stats()["pending"] == 1
+        q.release(t1)
+        i2 = q.wait(t2, 10)
+        assert i2["status"] == 0 and i2["t_admit_ns"] >= i1["t_done_ns"]
+        q.release(t2)
+        assert q.stats()["bytes_in_use"] == 0
+        assert q.poll(t1)[0] == 11                          # released -> not found
+
+
+def test_release_on_completion_frees_everything():
+    with sim_queue() as q:
+        tk = q.submit([syn_req(300, 40, key=k) for k in range(8)])
+        wait_all(q, tk)
+        assert q.stats()["bytes_in_use"] == 0
+
+
+def test_latency_statistics_match_records():
+    with sim_queue(rate_flops_per_ns=2000.0, fixed_ns=20_000.0) as q:
+        rng = np.random.default_rng(0)
+        reqs = [dev_req(int(m), int(n)) for m, n in zip(rng.integers(8, 600, 40), rng.integers(1, 200, 40))]
+        tk = q.submit(reqs)
+        infos = wait_all(q, tk)
+        st = q.stats()
+    lat = np.sort([i["t_done_ns"] - i["t_arrival_ns"] for i in infos])
+    assert st["completed"] == 40
+    assert st["p50_ns"] == lat[int(0.5 * 39 + 0.5)]
+    assert st["p99_ns"] == lat[int(0.99 * 39 + 0.5)]
+    assert st["max_ns"] == lat[-1]
+    assert abs(st["mean_ns"] - lat.mean()) <= 1e-6 * lat.mean()
+    assert st["solves_per_s"] > 0
+    assert all(i["t_arrival_ns"] <= i["t_admit_ns"] <= i["t_done_ns"] for i in infos)
+
+
+def test_scheduled_arrival_counts_toward_latency():
+    with sim_queue() as q:
+        t0 = hs.clock_ns()
+        t = q.submit(dev_req(32, 32, t_arrival_ns=t0 - 5 * MS))
+        i = q.wait(t, 10)
+    assert i["t_arrival_ns"] == t0 - 5 * MS
+    assert i["t_done_ns"] - i["t_arrival_ns"] >= 5 * MS
+
+
+def test_validation():
+    with sim_queue() as q:
+        bad = dev_req(32, 32)
+        bad.input = 7
+        with pytest.raises(hs.HsmaError) as e:
+            q.submit(bad)
+        assert e.value.status == 1
+        with pytest.raises(hs.HsmaError) as e:
+            q.submit(dev_req(0, 5))
+        assert e.value.status == 2
+        r = dev_req(32, 32)
+        r.prob.alpha_im = 1.0
+        with pytest.raises(hs.HsmaError) as e:
+            q.submit(r)
+        assert e.value.status == 1
+        r = dev_req(32, 32)
+        r.prob.A = None
+        with pytest.raises(hs.HsmaError) as e:
+            q.submit(r)
+        assert e.value.status == 3
+        r = dev_req(32, 32)
+        r.prob.lda = 16
+        with pytest.raises(hs.HsmaError) as e:
+            q.submit(r)
+        assert e.value.status == 2
+        r = syn_req(32, 32)
+        r.release_on_completion = 2
+        with pytest.raises(hs.HsmaError) as e:
+            q.submit(r)
+        assert e.value.status == 1
+        assert q.poll(12345)[0] == 11
+        with pytest.raises(hs.HsmaError) as e:
+            q.release(12345)
+        assert e.value.status == 11
+        assert q.stats()["submitted"] == 0
+
+
+def test_release_and_wait_while_running():
+    with sim_queue(rate_flops_per_ns=5.0) as q:      # 1.3e8 flops -> ~27 ms
+        t = q.submit(dev_req(512, 512))
+        with pytest.raises(hs.HsmaError) as e:
+            q.release(t)
+        assert e.value.status == 9
+        with pytest.raises(hs.HsmaError) as e:
+            q.wait(t, 0.001)
+        assert e.value.status == 10
+        assert q.wait(t, 20)["status"] == 0
+
+
+def test_concurrent_submitters():
+    with sim_queue(rate_flops_per_ns=50000.0) as q:
+        got = [[] for _ in range(4)]
+
+        def worker(k):
+            for i in range(50):
+                got[k].append(q.submit(dev_req(8 + (i * 7 + k) % 120, 1 + i % 30)))
+
+        ths = [threading.Thread(target=worker, args=(k,)) for k in range(4)]
+        for t in ths:
+            t.start()
+        for t in ths:
+            t.join()
+        tickets = [t for g in got for t in g]
+        assert len(set(tickets)) == 200
+        infos = wait_all(q, tickets)
+        assert all(i["status"] == 0 for i in infos)
+        assert q.stats()["completed"] == 200
+
+
+def test_destroy_with_unadmittable_pending_returns():
+    r = syn_req(512, 256, keep=True)
+    fp = hs.request_footprint(r)
+    q = sim_queue(hbm_budget_bytes=int(fp * 1.5))
+    t1, t2 = q.submit([syn_req(512, 256, key=1, keep=True), syn_req(512, 256, key=2, keep=True)])
+    q.wait(t1, 10)
+    t0 = time.time()
+    q.close()                                            # t2 can never be admitted
+    assert time.time() - t0 < 5.0
+
+
+def test_config_validation():
+    h = ctypes.c_void_p()
+    cfg = hs.QueueConfig(5, 0, 0, 0, 0, 0.0, 0.0)
+    assert hs.lib().hsma_queue_create(ctypes.byref(cfg), ctypes.byref(h)) == 1
+    cfg = hs.QueueConfig(hs.BACKEND_SIMULATED, -1, 0, 0, 0, 0.0, 0.0)
+    assert hs.lib().hsma_queue_create(ctypes.byref(cfg), ctypes.byref(h)) == 1
+    assert hs.lib().hsma_queue_create(ctypes.byref(cfg), None) == 3

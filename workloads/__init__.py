@@ -307,3 +307,91 @@ def serving_stream(seed: int = 4, rate: float = 20000.0, duration: float = 60.0,
     al = rng.uniform(alpha_range[0], alpha_range[1], size=k)
     return [Request(i, float(t[i]), int(ms[i]), int(ns[i]), bool(cx[i]), float(al[i]))
             for i in range(k)]
+
+
+# ---------------------------------------------------------------------------
+# Counter-based synthetic inputs (serving requests)
+# ---------------------------------------------------------------------------
+#
+# Philox4x32-10 (Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as
+# easy as 1, 2, 3", SC'11): a 4 x 32-bit counter and a 2 x 32-bit key go
+# through ten rounds; each round multiplies words 0 and 2 by fixed odd
+# constants, and the new words are (hi(M1 c2) ^ c1 ^ k0, lo(M1 c2),
+# hi(M0 c0) ^ c3 ^ k1, lo(M0 c0)); the key is bumped by two Weyl constants
+# between rounds.  The device library draws serving inputs with its own
+# implementation of the same published generator; this one lets the host
+# regenerate them for verification.
+
+PHILOX_M0, PHILOX_M1 = 0xD2511F53, 0xCD9E8D57
+PHILOX_W0, PHILOX_W1 = 0x9E3779B9, 0xBB67AE85
+_MASK32 = np.uint64(0xFFFFFFFF)
+
+
+def philox4x32_10(counter, key):
+    """Philox4x32-10 on arrays: ``counter`` is a sequence of four uint32
+    arrays (or scalars), ``key`` a pair of uint32 values.  Returns four
+    uint32 arrays."""
+    c = [np.asarray(x, dtype=np.uint64) & _MASK32 for x in counter]
+    k0, k1 = np.uint64(int(key[0]) & 0xFFFFFFFF), np.uint64(int(key[1]) & 0xFFFFFFFF)
+    m0, m1 = np.uint64(PHILOX_M0), np.uint64(PHILOX_M1)
+    w0, w1 = np.uint64(PHILOX_W0), np.uint64(PHILOX_W1)
+    for r in range(10):
+        if r:
+            k0 = (k0 + w0) & _MASK32
+            k1 = (k1 + w1) & _MASK32
+        p0 = m0 * c[0]            # < 2^64: exact in uint64
+        p1 = m1 * c[2]
+        c = [(p1 >> np.uint64(32)) ^ c[1] ^ k0, p1 & _MASK32,
+             (p0 >> np.uint64(32)) ^ c[3] ^ k1, p0 & _MASK32]
+    return [x.astype(np.uint32) for x in c]
+
+
+def philox_uniforms(e: np.ndarray, tag: int, key: int):
+    """Two 53-bit uniforms on [0, 1) per element index ``e`` (uint64 array):
+    counter (e mod 2^32, e div 2^32, tag, 0), key (key mod 2^32, key div 2^32);
+    u1 from output words (x0, x1), u2 from (x2, x3), each the top 53 bits of
+    the 64-bit word x_lo + 2^32 x_hi, times 2^-53."""
+    e = np.asarray(e, dtype=np.uint64)
+    x = philox4x32_10([e & _MASK32, e >> np.uint64(32), np.full(e.shape, tag, np.uint64),
+                       np.zeros(e.shape, np.uint64)],
+                      (key & 0xFFFFFFFF, (key >> 32) & 0xFFFFFFFF))
+    a = (x[1].astype(np.uint64) << np.uint64(32)) | x[0].astype(np.uint64)
+    b = (x[3].astype(np.uint64) << np.uint64(32)) | x[2].astype(np.uint64)
+    u1 = (a >> np.uint64(11)).astype(np.float64) * 2.0 ** -53
+    u2 = (b >> np.uint64(11)).astype(np.float64) * 2.0 ** -53
+    return u1, u2
+
+
+def serving_key(seed: int, rid: int) -> int:
+    """Philox key of serving request ``rid`` of a stream drawn with ``seed``."""
+    return ((seed & 0xFFFFFFFF) << 32) | (rid & 0xFFFFFFFF)
+
+
+def synthetic_inputs(m: int, n: int, key: int, complex_: bool = False):
+    """L (m x m) and B (m x n) of a synthetic serving request, column-major:
+    element e (column-major index) of L from philox_uniforms(e, 0, key), of B
+    from tag 1.  L: strict lower (2 u1 - 1)/m (complex: imaginary part
+    (2 u2 - 1)/m), diagonal 1 + u1 (complex: imaginary u2 - 1/2), upper
+    triangle 0.  B: sqrt(-2 ln(1 - u1)) cos(2 pi u2) (complex: imaginary part
+    with sin) -- the Box-Muller transform, so B ~ N(0, 1) as in the standard
+    workload, and L has its off-diagonal U(-1, 1)/m and diagonal U(1, 2)."""
+    e = np.arange(m * m, dtype=np.uint64)
+    u1, u2 = philox_uniforms(e, 0, key)
+    i = (e % np.uint64(max(m, 1))).astype(np.int64)
+    j = (e // np.uint64(max(m, 1))).astype(np.int64)
+    low, diag = i > j, i == j
+    re = np.where(low, (2.0 * u1 - 1.0) / m, np.where(diag, 1.0 + u1, 0.0))
+    if complex_:
+        im = np.where(low, (2.0 * u2 - 1.0) / m, np.where(diag, u2 - 0.5, 0.0))
+        L = (re + 1j * im).reshape(m, m, order="F")
+    else:
+        L = re.reshape(m, m, order="F")
+    eb = np.arange(m * n, dtype=np.uint64)
+    v1, v2 = philox_uniforms(eb, 1, key)
+    r = np.sqrt(-2.0 * np.log(1.0 - v1))
+    th = 6.283185307179586 * v2
+    if complex_:
+        B = (r * np.cos(th) + 1j * (r * np.sin(th))).reshape(m, n, order="F")
+    else:
+        B = (r * np.cos(th)).reshape(m, n, order="F")
+    return np.asfortranarray(L), np.asfortranarray(B)
