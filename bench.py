@@ -483,7 +483,8 @@ def run_serving(args, torch, hs):
         if time.time() - last_log > 2.0:
             s = q.stats()
             log(f"  t={(now - t0) * 1e-9:5.1f}s submitted {submitted} completed {s['completed']} "
-                f"pending {s['pending']} inflight {s['inflight']}")
+                f"pending {s['pending']} inflight {s['inflight']} rounds {s['rounds']} "
+                f"launch {s['launch_ms']:.0f} ms budget {s['bytes_in_use'] / 2**30:.1f} GiB")
             last_log = time.time()
     t_end_submit = hs.clock_ns()
     deadline = time.time() + max(60.0, 4 * duration)
@@ -492,7 +493,8 @@ def run_serving(args, torch, hs):
         if s["completed"] + s["failed"] >= N + len(wk) or time.time() > deadline:
             break
         if time.time() - last_log > 2.0:
-            log(f"  draining: completed {s['completed']} pending {s['pending']} inflight {s['inflight']}")
+            log(f"  draining: completed {s['completed']} pending {s['pending']} inflight {s['inflight']} "
+                f"rounds {s['rounds']} launch {s['launch_ms']:.0f} ms budget {s['bytes_in_use'] / 2**30:.1f} GiB")
             last_log = time.time()
         time.sleep(0.01)
     s = q.stats()
@@ -548,6 +550,7 @@ def run_serving(args, torch, hs):
                     "rejected": s["rejected"], "peak_budget_bytes": s["bytes_peak"],
                     "budget_bytes": 32 << 30, "saturated": saturated,
                     "drain_after_last_arrival_s": round(backlog_s, 3),
+                    "admission_rounds": s["rounds"], "scheduler_launch_ms": round(s["launch_ms"], 1),
                     "served_tflops": round(total_flops / span / 1e12, 3)},
         "extra_config": {"rate_per_s": rate, "duration_s": duration, "seed": seed,
                          "m_range": [8, 4096], "n_range": [1, 512], "p_complex": 0.3,

@@ -23,8 +23,8 @@
  *
  * Memory and streams:
  *   - A and B are DEVICE pointers owned by the caller.  A and B must not
- *     overlap.  The library owns its workspaces (stream-ordered allocations
- *     from the device's default memory pool).
+ *     overlap.  The library owns its workspaces (a per-device cache of device
+ *     blocks reused in stream order; see hsma_workspace_release).
  *   - Every call is asynchronous on `stream` (a hipStream_t passed as void*;
  *     NULL is the null stream): it returns after enqueueing and the result is
  *     complete when the stream reaches that point.  Exceptions noted per call.
@@ -168,6 +168,15 @@ hsma_status hsma_trsm_ex(hsma_diag diag, int64_t m, int64_t n, const void *alpha
 hsma_status hsma_graph_cache_clear(void);
 
 /*
+ * Workspace cache.  The library keeps freed workspace blocks of the current
+ * device (binned by size, reused in stream order) instead of returning them;
+ * this returns every idle block to the device, after waiting for its last
+ * use.  Blocks still in use stay.  The cache also trims itself when an
+ * allocation runs out of device memory.
+ */
+hsma_status hsma_workspace_release(void);
+
+/*
  * hsma_lookup_block_size -- the I_B the tuning table gives for (dtype, m, n):
  * the entry whose tested scale is nearest in log2(m), then log2(n), ties to
  * the smaller scale (Sec. 4.3.2, online phase).  Host-only; no device access.
@@ -199,10 +208,12 @@ typedef struct {
  * the hsma_trsm rules first; on the first invalid one its index goes to
  * *first_bad (if non-NULL), its status is returned and nothing is enqueued.
  * Problems with m <= 64 run in a handful of persistent grouped launches
- * (one per data type, diagonal kind and ceil(m/8)), forked onto
- * library-owned streams and joined back into `stream`; the rest take the
- * blocked path in order.  Asynchronous on `stream`.  The problems' B
- * matrices must not overlap each other or any A.
+ * (one per data type, diagonal kind and ceil(m/8)); the rest take the
+ * blocked path grouped: every problem keeps the schedule (I_B, inversions,
+ * recursion) it gets alone, so its result is bit-for-bit the same, but the
+ * k-th operation of all of them shares one launch.  Both parts are forked
+ * onto library-owned streams and joined back into `stream`.  Asynchronous on
+ * `stream`.  The problems' B matrices must not overlap each other or any A.
  */
 hsma_status hsma_trsm_batched(const hsma_problem *probs, int64_t count, int64_t *first_bad,
                               hsma_stream_t stream);
@@ -280,10 +291,11 @@ hsma_status hsma_generate_inputs(hsma_dtype dtype, int64_t m, int64_t n, uint64_
  *     and recording its latency (arrival to completion),
  *   - admits pending requests strictly in arrival order while the HBM budget
  *     and the in-flight limit allow,
- *   - launches each admission round: all its small requests (m <= 64) as one
- *     batched call (hsma_trsm_batched) on the queue's small stream, every
- *     larger request as its own blocked solve, round-robin over the queue's
- *     other streams.
+ *   - launches each admission round by size class (m <= 64; 64 < m <= 512;
+ *     m > 512), each class as one hsma_trsm_batched call with its own
+ *     completion event: the small class on the queue's small stream, the two
+ *     blocked classes round-robin over the queue's other streams.  Synthetic
+ *     inputs of a class are drawn in one launch on the class's stream first.
  * A request's footprint is its blocked-path workspace (a 4 KiB descriptor
  * share for small requests) plus, for synthetic requests, its L and B.
  */
@@ -337,6 +349,8 @@ typedef struct {
                                  percentile q is the sorted sample at rank
                                  round(q (count - 1)) */
     double solves_per_s;      /* completed / (last completion - first submit) */
+    int64_t rounds;           /* admission rounds that launched work */
+    double launch_ms;         /* scheduler time spent enqueueing work */
 } hsma_queue_statistics;
 
 typedef struct hsma_queue hsma_queue;

@@ -94,7 +94,8 @@ class QueueStatistics(ctypes.Structure):
                 ("bytes_in_use", ctypes.c_uint64), ("bytes_peak", ctypes.c_uint64),
                 ("p50_ns", ctypes.c_double), ("p99_ns", ctypes.c_double),
                 ("max_ns", ctypes.c_double), ("mean_ns", ctypes.c_double),
-                ("solves_per_s", ctypes.c_double)]
+                ("solves_per_s", ctypes.c_double), ("rounds", ctypes.c_int64),
+                ("launch_ms", ctypes.c_double)]
 
 
 BACKEND_HIP, BACKEND_SIMULATED = 0, 1
@@ -138,6 +139,8 @@ def lib():
         L.hsma_batch_plan_execute.restype = i32
         L.hsma_batch_plan_destroy.argtypes = [vp]
         L.hsma_batch_plan_destroy.restype = i32
+        L.hsma_workspace_release.argtypes = []
+        L.hsma_workspace_release.restype = i32
         L.hsma_graph_cache_clear.argtypes = []
         L.hsma_graph_cache_clear.restype = i32
         L.hsma_profile_begin.argtypes = []
@@ -402,6 +405,11 @@ def profile_end() -> dict:
 
 def graph_cache_clear() -> None:
     _check(lib().hsma_graph_cache_clear(), "hsma_graph_cache_clear")
+
+
+def workspace_release() -> None:
+    """Return the library's idle cached workspace blocks to the device."""
+    _check(lib().hsma_workspace_release(), "hsma_workspace_release")
 
 
 def lookup_block_size(complex_: bool, m: int, n: int) -> int:

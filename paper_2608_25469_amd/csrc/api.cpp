@@ -66,23 +66,6 @@ hsma_status device_info(DeviceInfo *out) {
     return HSMA_SUCCESS;
 }
 
-hsma_status ws_alloc(void **p, size_t bytes, hipStream_t s) {
-    *p = nullptr;
-    if (bytes == 0) return HSMA_SUCCESS;
-    hipError_t e = hipMallocAsync(p, bytes, s);
-    if (e == hipErrorOutOfMemory) {
-        (void)hipGetLastError();
-        return HSMA_ALLOC_FAILED;
-    }
-    HSMA_HIP(e);
-    return HSMA_SUCCESS;
-}
-
-hsma_status ws_free(void *p, hipStream_t s) {
-    if (p) HSMA_HIP(hipFreeAsync(p, s));
-    return HSMA_SUCCESS;
-}
-
 // Nearest tested scale in log2(m), then log2(n); ties go to the smaller scale.
 int lookup_block_size(bool cx, int64_t m, int64_t n) {
     const int dt = cx ? 1 : 0;

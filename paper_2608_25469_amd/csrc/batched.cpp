@@ -9,7 +9,7 @@
 // zeroed work counter per group in front, is uploaded in one copy; the group
 // launches are forked onto library-owned streams so they overlap on the
 // device, and joined back into the caller's stream.  Problems with m > 64
-// take the blocked path one by one on the caller's stream.
+// take the grouped blocked path (grouped.cpp) on one more forked stream.
 
 #include <algorithm>
 #include <cstring>
@@ -27,6 +27,9 @@ hsma_status trsm_impl(hsma_diag diag, int64_t m, int64_t n, const void *alpha, c
                       int64_t lda, void *B, int64_t ldb, hsma_dtype dtype, int ib_override,
                       int path, hipStream_t s, int *path_used, int *ib_used,
                       const hsma_trsm_options *opt, hsma_trsm_report *rep);
+
+// From grouped.cpp
+hsma_status grouped_blocked(const hsma_problem *probs, int64_t count, hipStream_t s);
 
 // From small_d.hip / small_z.hip
 hsma_status launch_small_group_d(bool unit, int nch, const void *items, int count,
@@ -61,16 +64,19 @@ struct DevicePool {
     hipStream_t fork[kForkStreams] = {};
     int occ[kGroups] = {};
     std::mutex mu;
-    // pinned staging ring
+    // Pinned staging buffers for descriptor uploads.  A buffer is reusable
+    // once the copy out of it has finished (its event); the pool grows up to
+    // kMaxStages rather than make the host wait for the device.
     struct Stage {
         void *host = nullptr;
         size_t bytes = 0;
         hipEvent_t done = nullptr;
         bool used = false;
     };
-    Stage stage[4];
-    int next = 0;
+    std::vector<Stage> stages;
+    size_t next = 0;  // wait-for-oldest victim once the pool is full
 };
+constexpr size_t kMaxStages = 64;
 DevicePool g_pools[64];
 
 hsma_status pool_for(DevicePool **out, int *cus) {
@@ -169,6 +175,22 @@ static void build_image(const hsma_problem *probs, int64_t count, BatchTable *t,
     }
 }
 
+// The problems with m > 64: grouped blocked launches for alpha != 0, the
+// single-problem path (a zero fill) for alpha == 0.
+static hsma_status run_large(const std::vector<hsma_problem> &large, hipStream_t s) {
+    std::vector<hsma_problem> grouped;
+    for (const hsma_problem &p : large) {
+        if (p.alpha_re == 0.0 && p.alpha_im == 0.0) {
+            double al[2] = {0.0, 0.0};
+            HSMA_TRY(trsm_impl((hsma_diag)p.diag, p.m, p.n, al, p.A, p.lda, p.B, p.ldb,
+                               (hsma_dtype)p.dtype, 0, 0, s, nullptr, nullptr, nullptr, nullptr));
+        } else {
+            grouped.push_back(p);
+        }
+    }
+    return grouped_blocked(grouped.data(), (int64_t)grouped.size(), s);
+}
+
 // Enqueue the grouped launches (and the large problems) on stream s.
 static hsma_status run_table(const BatchTable &t, hipStream_t s) {
     DevicePool *pool;
@@ -176,6 +198,7 @@ static hsma_status run_table(const BatchTable &t, hipStream_t s) {
     HSMA_TRY(pool_for(&pool, &cus));
     int ngroups = 0;
     for (int g = 0; g < kGroups; ++g) ngroups += t.count[g] > 0;
+    if (!t.large.empty()) ngroups += 1;
     if (ngroups > 0) {
         hipEvent_t fork_ev;
         HSMA_HIP(hipEventCreateWithFlags(&fork_ev, hipEventDisableTiming));
@@ -206,6 +229,18 @@ static hsma_status run_table(const BatchTable &t, hipStream_t s) {
                 joins.push_back(j);
             }
         }
+        // The large problems run beside the small groups.
+        if (st == HSMA_SUCCESS && !t.large.empty()) {
+            hipStream_t fs = ngroups == 1 ? s : pool->fork[k++ % kForkStreams];
+            if (fs != s) HSMA_HIP(hipStreamWaitEvent(fs, fork_ev, 0));
+            st = run_large(t.large, fs);
+            if (fs != s) {
+                hipEvent_t j;
+                HSMA_HIP(hipEventCreateWithFlags(&j, hipEventDisableTiming));
+                HSMA_HIP(hipEventRecord(j, fs));
+                joins.push_back(j);
+            }
+        }
         for (hipEvent_t j : joins) {
             HSMA_HIP(hipStreamWaitEvent(s, j, 0));
             HSMA_HIP(hipEventDestroy(j));
@@ -213,36 +248,61 @@ static hsma_status run_table(const BatchTable &t, hipStream_t s) {
         HSMA_HIP(hipEventDestroy(fork_ev));
         HSMA_TRY(st);
     }
-    for (const hsma_problem &p : t.large) {
-        double al[2] = {p.alpha_re, p.alpha_im};
-        HSMA_TRY(trsm_impl((hsma_diag)p.diag, p.m, p.n, al, p.A, p.lda, p.B, p.ldb,
-                           (hsma_dtype)p.dtype, 0, 0, s, nullptr, nullptr, nullptr, nullptr));
-    }
     return HSMA_SUCCESS;
 }
 
-// Upload the image through a pinned staging buffer (asynchronous on s).
-static hsma_status upload(const std::vector<unsigned char> &img, void *dev, hipStream_t s) {
+// Copy `bytes` of host data to device memory `dev` through a pinned staging
+// buffer, asynchronously on s (the host data may be reused on return).
+hsma_status upload_async(const void *host, size_t bytes, void *dev, hipStream_t s) {
+    if (bytes == 0) return HSMA_SUCCESS;
     DevicePool *pool;
     int cus;
     HSMA_TRY(pool_for(&pool, &cus));
     std::lock_guard<std::mutex> lk(pool->mu);
-    DevicePool::Stage &st = pool->stage[pool->next];
-    pool->next = (pool->next + 1) % 4;
-    if (st.used) HSMA_HIP(hipEventSynchronize(st.done));  // previous copy from it finished
-    if (st.bytes < img.size()) {
+    auto idle = [](DevicePool::Stage &x) {
+        if (!x.used) return true;
+        const hipError_t e = hipEventQuery(x.done);
+        if (e == hipSuccess) {
+            x.used = false;
+            return true;
+        }
+        if (e != hipErrorNotReady) (void)hipGetLastError();
+        return false;
+    };
+    // Smallest idle buffer that is large enough.
+    DevicePool::Stage *pick = nullptr;
+    for (DevicePool::Stage &x : pool->stages)
+        if (x.bytes >= bytes && idle(x) && (!pick || x.bytes < pick->bytes)) pick = &x;
+    if (!pick && pool->stages.size() < kMaxStages) {
+        pool->stages.emplace_back();
+        pick = &pool->stages.back();
+    }
+    if (!pick) {
+        // Pool full: wait for the oldest victim, then size it.
+        pick = &pool->stages[pool->next];
+        pool->next = (pool->next + 1) % pool->stages.size();
+        if (pick->used) HSMA_HIP(hipEventSynchronize(pick->done));
+        pick->used = false;
+    }
+    DevicePool::Stage &st = *pick;
+    if (st.bytes < bytes) {
         if (st.host) HSMA_HIP(hipHostFree(st.host));
         st.host = nullptr;
-        size_t want = std::max<size_t>(img.size(), 1 << 20);
+        st.bytes = 0;
+        size_t want = std::max<size_t>(bytes, 1 << 20);
         HSMA_HIP(hipHostMalloc(&st.host, want, hipHostMallocDefault));
         st.bytes = want;
     }
     if (!st.done) HSMA_HIP(hipEventCreateWithFlags(&st.done, hipEventDisableTiming));
-    std::memcpy(st.host, img.data(), img.size());
-    HSMA_HIP(hipMemcpyAsync(dev, st.host, img.size(), hipMemcpyHostToDevice, s));
+    std::memcpy(st.host, host, bytes);
+    HSMA_HIP(hipMemcpyAsync(dev, st.host, bytes, hipMemcpyHostToDevice, s));
     HSMA_HIP(hipEventRecord(st.done, s));
     st.used = true;
     return HSMA_SUCCESS;
+}
+
+static hsma_status upload(const std::vector<unsigned char> &img, void *dev, hipStream_t s) {
+    return upload_async(img.data(), img.size(), dev, s);
 }
 
 }  // namespace hsma

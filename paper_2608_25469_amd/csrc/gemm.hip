@@ -45,21 +45,6 @@ struct __attribute__((aligned(8))) d2 {
     double x, y;
 };
 
-struct GemmParams {
-    int M, N, K;          // real-view sizes
-    const double *A;
-    int64_t lda;          // real: doubles; complex: complex elements
-    const double *B;
-    int64_t ldb;          // doubles
-    double *C;
-    int64_t ldc;          // doubles
-    double alpha_re, alpha_im, beta_re, beta_im;
-    int tri_a;            // 0 plain, 1 lower non-unit, 2 lower unit (diagonal block of L)
-    int inner;            // batch decomposition
-    int64_t a_outer, a_inner, b_outer, b_inner, c_outer, c_inner;
-    int tiles_m, tiles_n;
-};
-
 constexpr int BK = 16;
 
 // Workgroups per CU that the tile's LDS ring allows (160 KB per CU, at most
@@ -78,8 +63,12 @@ __host__ __device__ constexpr int occ_for(int bm, int bn) {
 #define HSMA_UPD_WN 2
 #endif
 
-template <bool CX, int BM, int BN, int WM, int WN, int ROLE>
-__global__ __launch_bounds__(256, (occ_for(BM, BN))) void hsma_gemm(const GemmParams p) {
+// One BM x BN tile (tm, tn) of C = beta C + alpha A B; Ag, Bg, Cg are the
+// operand bases of this product (after any batch offset).
+template <bool CX, int BM, int BN, int WM, int WN>
+__device__ __forceinline__ void gemm_tile(const GemmParams &p, const double *__restrict__ Ag,
+                                          const double *__restrict__ Bg, double *__restrict__ Cg,
+                                          int tm, int tn) {
     constexpr int TM = BM / WM, TN = BN / WN;
     constexpr int FM = TM / 16, FN = TN / 16;
     constexpr int LDA_S = BM + 4;    // LDS stride of the A tile (per k)
@@ -89,27 +78,6 @@ __global__ __launch_bounds__(256, (occ_for(BM, BN))) void hsma_gemm(const GemmPa
 
     __shared__ double As[2][BK * LDA_S];
     __shared__ double Bs[2][BN * LDB_S];
-
-    // ---- tile selection (XCD-aware, grouped) ----
-    const int T = p.tiles_m * p.tiles_n;
-    const int bid = blockIdx.x;
-    const int nb = gridDim.x;  // multiple of 8
-    const int per = nb / 8;
-    const int t = (bid % 8) * per + bid / 8;
-    if (t >= T) return;
-    constexpr int GROUP = 8;
-    const int gsz_full = GROUP * p.tiles_n;
-    const int g = t / gsz_full;
-    const int first = g * GROUP;
-    const int gsize = (p.tiles_m - first) < GROUP ? (p.tiles_m - first) : GROUP;
-    const int tm = first + (t % gsz_full) % gsize;
-    const int tn = (t % gsz_full) / gsize;
-
-    const int batch = blockIdx.y;
-    const int bo = batch / p.inner, bi = batch % p.inner;
-    const double *__restrict__ Ag = p.A + bo * p.a_outer + bi * p.a_inner;
-    const double *__restrict__ Bg = p.B + bo * p.b_outer + bi * p.b_inner;
-    double *__restrict__ Cg = p.C + bo * p.c_outer + bi * p.c_inner;
 
     const int m0 = tm * BM, n0 = tn * BN;
     const int M = p.M, N = p.N, K = p.K;
@@ -309,6 +277,50 @@ __global__ __launch_bounds__(256, (occ_for(BM, BN))) void hsma_gemm(const GemmPa
             }
         }
     }
+}
+
+template <bool CX, int BM, int BN, int WM, int WN, int ROLE>
+__global__ __launch_bounds__(256, (occ_for(BM, BN))) void hsma_gemm(const GemmParams p) {
+    // Tile selection, XCD-aware: consecutive workgroup ids land on different
+    // XCDs, so ids are remapped to give each XCD a contiguous run of tiles,
+    // walked in groups of 8 tile-rows.
+    const int T = p.tiles_m * p.tiles_n;
+    const int bid = blockIdx.x;
+    const int nb = gridDim.x;  // multiple of 8
+    const int per = nb / 8;
+    const int t = (bid % 8) * per + bid / 8;
+    if (t >= T) return;
+    constexpr int GROUP = 8;
+    const int gsz_full = GROUP * p.tiles_n;
+    const int g = t / gsz_full;
+    const int first = g * GROUP;
+    const int gsize = (p.tiles_m - first) < GROUP ? (p.tiles_m - first) : GROUP;
+    const int tm = first + (t % gsz_full) % gsize;
+    const int tn = (t % gsz_full) / gsize;
+    const int batch = blockIdx.y;
+    const int bo = batch / p.inner, bi = batch % p.inner;
+    gemm_tile<CX, BM, BN, WM, WN>(p, p.A + bo * p.a_outer + bi * p.a_inner,
+                                  p.B + bo * p.b_outer + bi * p.b_inner,
+                                  p.C + bo * p.c_outer + bi * p.c_inner, tm, tn);
+}
+
+// Grouped launch: descriptor d owns tiles [d.tile0, d.tile0 + tiles_m
+// tiles_n) of the grid; each workgroup finds its descriptor by binary search
+// over the ascending tile0 values and computes one tile of that product.
+template <bool CX, int BM, int BN, int WM, int WN>
+__global__ __launch_bounds__(256, (occ_for(BM, BN))) void hsma_gemm_grouped(
+    const GemmParams *__restrict__ descs, int nd) {
+    const int t = blockIdx.x;
+    int lo = 0, hi = nd - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (descs[mid].tile0 <= t) lo = mid;
+        else hi = mid - 1;
+    }
+    const GemmParams p = descs[lo];
+    const int local = t - p.tile0;
+    if (local < 0 || local >= p.tiles_m * p.tiles_n) return;
+    gemm_tile<CX, BM, BN, WM, WN>(p, p.A, p.B, p.C, local % p.tiles_m, local / p.tiles_m);
 }
 
 template <bool CX, int BM, int BN, int WM, int WN, int ROLE>
@@ -555,7 +567,63 @@ hsma_status launch_mixed(GemmParams p, int count, hipStream_t s) {
     return HSMA_SUCCESS;
 }
 
+template <bool CX, int BM, int BN, int WM, int WN>
+hsma_status grouped_t(const GemmParams *descs, int nd, int64_t tiles, int phase, double flops,
+                      hipStream_t s) {
+    ProfScope prof(phase, flops, s);
+    hipLaunchKernelGGL((hsma_gemm_grouped<CX, BM, BN, WM, WN>), dim3((unsigned)tiles), dim3(256), 0,
+                       s, descs, nd);
+    HSMA_HIP(hipGetLastError());
+    return HSMA_SUCCESS;
+}
+
+template <bool CX>
+hsma_status grouped_shape(GemmRole role, int bm, int bn, const GemmParams *descs, int nd,
+                          int64_t tiles, double flops, hipStream_t s) {
+    const int phase = role == GemmRole::Update    ? HSMA_PHASE_UPDATE
+                      : role == GemmRole::Leaf    ? HSMA_PHASE_LEAF
+                      : role == GemmRole::Inverse ? HSMA_PHASE_DIAG_INV
+                                                  : HSMA_PHASE_OTHER;
+    if (bm == 128 && bn == 32) return grouped_t<CX, 128, 32, 4, 1>(descs, nd, tiles, phase, flops, s);
+    if (bm == 256 && bn == 32) return grouped_t<CX, 256, 32, 4, 1>(descs, nd, tiles, phase, flops, s);
+    if (bm == 512 && bn == 16) return grouped_t<CX, 512, 16, 4, 1>(descs, nd, tiles, phase, flops, s);
+    if (bm == 64 && bn == 64) return grouped_t<CX, 64, 64, 2, 2>(descs, nd, tiles, phase, flops, s);
+    if (bm == 128 && bn == 64) return grouped_t<CX, 128, 64, 2, 2>(descs, nd, tiles, phase, flops, s);
+    if (bm == 128 && bn == 128) return grouped_t<CX, 128, 128, 2, 2>(descs, nd, tiles, phase, flops, s);
+    return HSMA_NOT_SUPPORTED;
+}
+
 }  // namespace
+
+int gemm_grouped_tile(GemmRole role, int max_m, int max_n, int *bm, int *bn) {
+    if (role == GemmRole::Leaf) {
+        if (max_m <= 128) { *bm = 128; *bn = 32; return 1; }
+        if (max_m <= 256) { *bm = 256; *bn = 32; return 1; }
+        if (max_m <= 512) { *bm = 512; *bn = 16; return 1; }
+        return 0;
+    }
+    if (role == GemmRole::UpdateMixed) return 0;
+    // Narrow right-hand sides: one column tile covers them, so each row
+    // panel of A is read once.
+    if (max_n <= 32) { *bm = max_m <= 128 ? 128 : 256; *bn = 32; return 1; }
+    if (max_n <= 64) { *bm = max_m <= 64 ? 64 : 128; *bn = 64; return 1; }
+    *bm = 128;
+    *bn = 128;
+    return 1;
+}
+
+int gemm_grouped_bucket(GemmRole role, int n) {
+    if (role == GemmRole::Leaf) return 0;
+    return n <= 32 ? 0 : (n <= 64 ? 1 : 2);
+}
+
+hsma_status launch_gemm_grouped(bool cplx_, GemmRole role, int bm, int bn, const GemmParams *descs,
+                                int nd, int64_t total_tiles, double flops, hipStream_t s) {
+    if (nd <= 0 || total_tiles <= 0) return HSMA_SUCCESS;
+    if (total_tiles > 0x7fffffff) return HSMA_INVALID_SIZE;
+    return cplx_ ? grouped_shape<true>(role, bm, bn, descs, nd, total_tiles, flops, s)
+                 : grouped_shape<false>(role, bm, bn, descs, nd, total_tiles, flops, s);
+}
 
 hsma_status launch_gemm(bool cplx_, GemmRole role, int M, int N, int K, cplx alpha,
                         const double *A, int64_t lda, const double *B, int64_t ldb, cplx beta,

@@ -13,6 +13,8 @@
 // upper triangle 0; B = sqrt(-2 ln(1 - u1)) cos(2 pi u2) (complex: imaginary
 // part with sin).  Column-major, lda = ldb = m.
 
+#include <vector>
+
 #include "internal.h"
 
 namespace hsma {
@@ -45,48 +47,82 @@ __device__ __forceinline__ void uniforms(uint64_t e, uint32_t tag, uint64_t key,
     *u2 = (double)(b >> 11) * 0x1.0p-53;
 }
 
+// L element (i, j), column-major index t = i + j m.
+__device__ __forceinline__ void gen_l(int cx, int64_t m, uint64_t key, double *__restrict__ L,
+                                      int64_t i, int64_t j) {
+    const int64_t t = i + j * m;
+    double u1, u2;
+    uniforms((uint64_t)t, 0u, key, &u1, &u2);
+    double re, im;
+    if (i > j) {
+        re = (2.0 * u1 - 1.0) / (double)m;
+        im = (2.0 * u2 - 1.0) / (double)m;
+    } else if (i == j) {
+        re = 1.0 + u1;
+        im = u2 - 0.5;
+    } else {
+        re = im = 0.0;
+    }
+    if (cx) {
+        L[2 * t] = re;
+        L[2 * t + 1] = im;
+    } else {
+        L[t] = re;
+    }
+}
+
+// B element with column-major index e.
+__device__ __forceinline__ void gen_b(int cx, uint64_t key, double *__restrict__ B, int64_t e) {
+    double u1, u2;
+    uniforms((uint64_t)e, 1u, key, &u1, &u2);
+    const double r = sqrt(-2.0 * log(1.0 - u1));
+    const double th = 6.283185307179586 * u2;
+    if (cx) {
+        B[2 * e] = r * cos(th);
+        B[2 * e + 1] = r * sin(th);
+    } else {
+        B[e] = r * cos(th);
+    }
+}
+
 __global__ __launch_bounds__(256) void hsma_gen_inputs(int cx, int64_t m, int64_t n, uint64_t key,
                                                        double *__restrict__ L,
                                                        double *__restrict__ B) {
     const int64_t nl = m * m, total = nl + m * n;
-    const double dm = (double)m;
     for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < total;
          t += (int64_t)gridDim.x * 256) {
         if (t < nl) {
-            const int64_t j = t / m, i = t - j * m;
-            double u1, u2;
-            uniforms((uint64_t)t, 0u, key, &u1, &u2);
-            double re, im;
-            if (i > j) {
-                re = (2.0 * u1 - 1.0) / dm;
-                im = (2.0 * u2 - 1.0) / dm;
-            } else if (i == j) {
-                re = 1.0 + u1;
-                im = u2 - 0.5;
-            } else {
-                re = im = 0.0;
-            }
-            if (cx) {
-                L[2 * t] = re;
-                L[2 * t + 1] = im;
-            } else {
-                L[t] = re;
-            }
+            const int64_t j = t / m;
+            gen_l(cx, m, key, L, t - j * m, j);
         } else {
-            const int64_t e = t - nl;
-            double u1, u2;
-            uniforms((uint64_t)e, 1u, key, &u1, &u2);
-            const double r = sqrt(-2.0 * log(1.0 - u1));
-            const double th = 6.283185307179586 * u2;
-            if (cx) {
-                B[2 * e] = r * cos(th);
-                B[2 * e + 1] = r * sin(th);
-            } else {
-                B[e] = r * cos(th);
-            }
+            gen_b(cx, key, B, t - nl);
         }
     }
 }
+
+// Many requests in one launch: workgroup b fills columns [j0, j1) of L
+// (which = 0) or of B (which = 1) of the request items[b] describes; the
+// threads walk the rows of each column, so no index division is needed.
+struct GenItem {
+    double *L, *B;
+    int64_t m;
+    uint64_t key;
+    int64_t j0, j1;
+    int32_t cx, which;
+};
+
+__global__ __launch_bounds__(256) void hsma_gen_group(const GenItem *__restrict__ items) {
+    const GenItem it = items[blockIdx.x];
+    for (int64_t j = it.j0; j < it.j1; ++j) {
+        if (it.which == 0) {
+            for (int64_t i = threadIdx.x; i < it.m; i += 256) gen_l(it.cx, it.m, it.key, it.L, i, j);
+        } else {
+            for (int64_t i = threadIdx.x; i < it.m; i += 256) gen_b(it.cx, it.key, it.B, i + j * it.m);
+        }
+    }
+}
+
+constexpr int64_t kGenChunk = 256 * 32;  // elements per workgroup of a grouped launch
 
 }  // namespace
 
@@ -101,6 +137,48 @@ hsma_status launch_gen_inputs(bool cx, int64_t m, int64_t n, uint64_t key, doubl
                        key, L, B);
     HSMA_HIP(hipGetLastError());
     return HSMA_SUCCESS;
+}
+
+hsma_status upload_async(const void *host, size_t bytes, void *dev, hipStream_t s);
+
+// Fill the inputs of many synthetic requests with one launch on s.
+hsma_status gen_inputs_grouped(const GenRequest *reqs, int count, hipStream_t s) {
+    std::vector<GenItem> items;
+    for (int i = 0; i < count; ++i) {
+        const GenRequest &r = reqs[i];
+        if (r.m <= 0) continue;
+        const int64_t cols = kGenChunk / r.m > 1 ? kGenChunk / r.m : 1;
+        for (int which = 0; which < 2; ++which) {
+            const int64_t nc = which == 0 ? r.m : r.n;
+            for (int64_t j0 = 0; j0 < nc; j0 += cols) {
+                GenItem it;
+                it.L = r.L;
+                it.B = r.B;
+                it.m = r.m;
+                it.key = r.key;
+                it.j0 = j0;
+                it.j1 = j0 + cols < nc ? j0 + cols : nc;
+                it.cx = r.cx ? 1 : 0;
+                it.which = which;
+                items.push_back(it);
+            }
+        }
+    }
+    if (items.empty()) return HSMA_SUCCESS;
+    if (items.size() > 0x7fffffff) return HSMA_INVALID_SIZE;
+    void *dev = nullptr;
+    const size_t bytes = items.size() * sizeof(GenItem);
+    HSMA_TRY(ws_alloc(&dev, bytes, s));
+    hsma_status st = upload_async(items.data(), bytes, dev, s);
+    if (st == HSMA_SUCCESS) {
+        ProfScope prof(HSMA_PHASE_OTHER, 0.0, s);
+        hipLaunchKernelGGL(hsma_gen_group, dim3((unsigned)items.size()), dim3(256), 0, s,
+                           static_cast<const GenItem *>(dev));
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) st = hip_fail(e);
+    }
+    const hsma_status st2 = ws_free(dev, s);
+    return st != HSMA_SUCCESS ? st : st2;
 }
 
 }  // namespace hsma

@@ -52,9 +52,12 @@ class ProfScope {
     int idx_;
 };
 
-// Stream-ordered workspace from the device's default memory pool.
+// Workspace from the library's per-device block cache (alloc.cpp): usable
+// in stream order on s; ws_free hands the block back after the work already
+// enqueued on s.
 hsma_status ws_alloc(void **p, size_t bytes, hipStream_t s);
 hsma_status ws_free(void *p, hipStream_t s);
+size_t ws_cached_bytes();
 
 // ---------------------------------------------------------------------------
 // Kernel launchers (each enqueues on `s`; arguments already validated).
@@ -77,11 +80,43 @@ hsma_status launch_zero(int64_t m, int64_t n, int es, double *B, int64_t ldb, hi
 // (b / inner) * s_outer + (b % inner) * s_inner (in doubles) for each operand.
 // tri_a: A is the m x m diagonal block of a lower-triangular matrix, read only
 // on and below its diagonal (0: plain, 1: lower non-unit, 2: lower unit).
+enum class GemmRole { Update = 0, Leaf = 1, Inverse = 2, Residual = 3, UpdateMixed = 4 };
+
+// Parameters of one product (also the descriptor of a grouped launch, read
+// by the kernel from device memory).
+struct GemmParams {
+    int M, N, K;          // real-view sizes
+    const double *A;
+    int64_t lda;          // real: doubles; complex: complex elements
+    const double *B;
+    int64_t ldb;          // doubles
+    double *C;
+    int64_t ldc;          // doubles
+    double alpha_re, alpha_im, beta_re, beta_im;
+    int tri_a;            // 0 plain, 1 lower non-unit, 2 lower unit (diagonal block of L)
+    int inner;            // batch decomposition
+    int64_t a_outer, a_inner, b_outer, b_inner, c_outer, c_inner;
+    int tiles_m, tiles_n;
+    int tile0;            // grouped launch: first tile of this product in the grid
+};
+
+// Tile shape a grouped launch of `role` uses when its largest product has
+// max_m real-view rows and max_n columns (leaves need one tile to span all
+// rows); 0 if unsupported.
+int gemm_grouped_tile(GemmRole role, int max_m, int max_n, int *bm, int *bn);
+// Products of one grouped step are split into launches by column count;
+// returns the bucket (0, 1, 2) of a product with n columns.
+int gemm_grouped_bucket(GemmRole role, int n);
+// Launch over nd descriptors already in device memory (tile0 / tiles_m /
+// tiles_n filled for the shape gemm_grouped_tile returned); total_tiles is
+// the grid size.  flops is for the phase profiler.
+hsma_status launch_gemm_grouped(bool cplx_, GemmRole role, int bm, int bn, const GemmParams *descs,
+                                int nd, int64_t total_tiles, double flops, hipStream_t s);
+
 struct GemmBatch {
     int count = 1, inner = 1;
     int64_t a_outer = 0, a_inner = 0, b_outer = 0, b_inner = 0, c_outer = 0, c_inner = 0;
 };
-enum class GemmRole { Update = 0, Leaf = 1, Inverse = 2, Residual = 3, UpdateMixed = 4 };
 hsma_status launch_gemm(bool cplx_, GemmRole role, int M, int N, int K,
                         cplx alpha, const double *A, int64_t lda, const double *B,
                         int64_t ldb, cplx beta, double *C, int64_t ldc, int tri_a,
@@ -94,5 +129,16 @@ hsma_status launch_gemm(bool cplx_, GemmRole role, int M, int N, int K,
 // Every element of W's ib x ib blocks not written by this call is zeroed.
 hsma_status launch_diag_inv_base(bool cplx_, bool unit, int m, int base, int ib,
                                  const double *A, int64_t lda, double *W, hipStream_t s);
+
+// Synthetic serving inputs (Philox4x32-10, see hsma_generate_inputs).
+struct GenRequest {
+    double *L, *B;   // lda = ldb = m
+    int64_t m, n;
+    uint64_t key;
+    bool cx;
+};
+hsma_status launch_gen_inputs(bool cx, int64_t m, int64_t n, uint64_t key, double *L, double *B,
+                              hipStream_t s);
+hsma_status gen_inputs_grouped(const GenRequest *reqs, int count, hipStream_t s);
 
 }  // namespace hsma

@@ -8,9 +8,11 @@
 //      in-flight limit allow (a request larger than the whole budget is
 //      rejected at submit, so the head of the queue always fits once the
 //      work ahead of it retires),
-//   3. launches what it admitted: all small requests (m <= 64) of the round
-//      as one batched call, every larger request as its own blocked solve on
-//      one of several streams,
+//   3. launches what it admitted by size class -- m <= 64, 64 < m <= 512,
+//      m > 512 -- each class as one batched call (persistent small-solve
+//      groups, or grouped blocked launches that advance all of the class's
+//      problems together) on its own stream, the two blocked classes
+//      round-robin over the queue's streams,
 // so requests arriving while others run reach the device as soon as slots
 // and memory free up, and their work overlaps on the GPU.
 //
@@ -37,8 +39,6 @@ size_t blocked_workspace_bytes(bool cx, int64_t m, int ib);
 int lookup_block_size(bool cx, int64_t m, int64_t n);
 hsma_status validate(int diag, int dtype, int64_t m, int64_t n, const void *alpha, const void *A,
                      int64_t lda, const void *B, int64_t ldb, bool *quick);
-hsma_status launch_gen_inputs(bool cx, int64_t m, int64_t n, uint64_t key, double *L, double *B,
-                              hipStream_t s);
 
 namespace {
 
@@ -65,13 +65,23 @@ size_t footprint(const hsma_request &r) {
     return f;
 }
 
+// Device memory shared by the auto-released synthetic requests of one size
+// class of one admission round (one allocation instead of one per request);
+// freed when the last of them finishes.
+struct Block {
+    void *mem = nullptr;
+    hipStream_t s = nullptr;
+    int refs = 0;
+};
+
 struct Req {
     uint64_t ticket = 0;
     hsma_request r{};
     double t_arrival = 0, t_admit = 0, t_done = 0;
     size_t held = 0;          // budget this request holds now
-    void *mem = nullptr;      // server allocation (synthetic inputs)
+    void *mem = nullptr;      // own server allocation (kept synthetic results)
     hipStream_t mem_stream = nullptr;
+    Block *blk = nullptr;     // shared allocation (auto-released synthetic inputs)
     const double *A = nullptr;
     double *B = nullptr;
     int64_t lda = 0, ldb = 0;
@@ -106,20 +116,41 @@ struct hsma_queue {
     std::vector<hipStream_t> streams;
     size_t rr = 0;
     std::vector<double> sim_free_at;  // simulation: per-stream busy-until (last = small)
+    // Device frees decided under the lock, issued after it is released.
+    std::vector<std::pair<void *, hipStream_t>> deferred;
     // statistics
     std::vector<double> latencies_ns;
-    int64_t submitted = 0, rejected = 0, completed = 0, failed = 0;
-    double t_first_submit = 0, t_last_done = 0;
+    int64_t submitted = 0, rejected = 0, completed = 0, failed = 0, rounds = 0;
+    double t_first_submit = 0, t_last_done = 0, launch_ns = 0;
 };
 
 namespace hsma {
 namespace {
 
-void free_mem(Req *r) {
+// Drop the request's hold on server memory (lock held); the actual frees
+// are queued for free_deferred.
+void release_mem(hsma_queue *q, Req *r) {
     if (r->mem) {
-        (void)ws_free(r->mem, r->mem_stream);
+        q->deferred.emplace_back(r->mem, r->mem_stream);
         r->mem = nullptr;
     }
+    if (r->blk) {
+        if (--r->blk->refs == 0) {
+            if (r->blk->mem) q->deferred.emplace_back(r->blk->mem, r->blk->s);
+            delete r->blk;
+        }
+        r->blk = nullptr;
+    }
+}
+
+// Issue the queued frees; takes and releases the lock itself.
+void free_deferred(hsma_queue *q, std::unique_lock<std::mutex> &lk) {
+    if (q->deferred.empty()) return;
+    std::vector<std::pair<void *, hipStream_t>> fr;
+    fr.swap(q->deferred);
+    lk.unlock();
+    for (auto &f : fr) (void)ws_free(f.first, f.second);
+    lk.lock();
 }
 
 // Called with the lock held.
@@ -138,125 +169,138 @@ void finish(hsma_queue *q, Req *r, double t, hsma_status st) {
     const bool keep = st == HSMA_SUCCESS && r->r.input == HSMA_INPUT_SYNTHETIC &&
                       !r->r.release_on_completion;
     const size_t keep_bytes = keep ? data_bytes(r->r.prob) : 0;
-    if (!keep) free_mem(r);
+    if (!keep) release_mem(q, r);
     q->budget_used -= r->held - keep_bytes;
     r->held = keep_bytes;
 }
 
+// Size classes of one admission round.  Each class is one batched call on
+// its own stream with its own completion event, so a round's small solves do
+// not wait for its largest blocked solve.
+int size_class(const hsma_problem &p) { return p.m <= 64 ? 0 : (p.m <= 512 ? 1 : 2); }
+constexpr int kClasses = 3;
+
 // Enqueue the admitted requests (HIP backend).  Called without the lock.
 void launch_admitted(hsma_queue *q, std::vector<Req *> &adm) {
-    std::vector<Req *> small;
-    std::vector<hsma_problem> small_probs;
-    for (Req *r : adm) {
-        const hsma_problem &p = r->r.prob;
-        const bool cx = p.dtype == HSMA_C64F;
-        hipStream_t s = p.m <= 64 ? q->small_stream : q->streams[q->rr++ % q->streams.size()];
-        hsma_status st = HSMA_SUCCESS;
-        if (r->r.input == HSMA_INPUT_SYNTHETIC) {
-            st = ws_alloc(&r->mem, data_bytes(p), s);
-            if (st == HSMA_SUCCESS) {
-                r->mem_stream = s;
-                r->A = static_cast<double *>(r->mem);
-                r->B = static_cast<double *>(r->mem) + (cx ? 2 : 1) * p.m * p.m;
+    std::vector<Req *> cls[kClasses];
+    for (Req *r : adm) cls[size_class(r->r.prob)].push_back(r);
+    for (int c = 0; c < kClasses; ++c) {
+        if (cls[c].empty()) continue;
+        hipStream_t s = c == 0 ? q->small_stream : q->streams[q->rr++ % q->streams.size()];
+        // One allocation for the class's auto-released synthetic inputs.
+        size_t shared_bytes = 0;
+        for (Req *r : cls[c])
+            if (r->r.input == HSMA_INPUT_SYNTHETIC && r->r.release_on_completion)
+                shared_bytes += (data_bytes(r->r.prob) + 255) / 256 * 256;
+        Block *blk = nullptr;
+        hsma_status blk_st = HSMA_SUCCESS;
+        if (shared_bytes) {
+            blk = new Block();
+            blk->s = s;
+            blk_st = ws_alloc(&blk->mem, shared_bytes, s);
+        }
+        size_t blk_off = 0;
+        std::vector<Req *> run;
+        std::vector<GenRequest> gen;
+        for (Req *r : cls[c]) {
+            const hsma_problem &p = r->r.prob;
+            const bool cx = p.dtype == HSMA_C64F;
+            r->path = p.m <= 64 ? 1 : 2;
+            if (r->r.input == HSMA_INPUT_SYNTHETIC) {
+                unsigned char *mem = nullptr;
+                hsma_status st = HSMA_SUCCESS;
+                if (r->r.release_on_completion) {
+                    st = blk_st;
+                    if (st == HSMA_SUCCESS) {
+                        mem = static_cast<unsigned char *>(blk->mem) + blk_off;
+                        blk_off += (data_bytes(p) + 255) / 256 * 256;
+                        r->blk = blk;
+                        blk->refs++;
+                    }
+                } else {
+                    st = ws_alloc(&r->mem, data_bytes(p), s);
+                    if (st == HSMA_SUCCESS) {
+                        r->mem_stream = s;
+                        mem = static_cast<unsigned char *>(r->mem);
+                    } else {
+                        r->mem = nullptr;
+                    }
+                }
+                if (st != HSMA_SUCCESS) {
+                    std::lock_guard<std::mutex> lk(q->mu);
+                    finish(q, r, clock_ns(), st);
+                    continue;
+                }
+                r->A = reinterpret_cast<double *>(mem);
+                r->B = reinterpret_cast<double *>(mem) + (cx ? 2 : 1) * p.m * p.m;
                 r->lda = r->ldb = p.m;
-                st = launch_gen_inputs(cx, p.m, p.n, r->r.key, const_cast<double *>(r->A), r->B, s);
+                gen.push_back(GenRequest{const_cast<double *>(r->A), r->B, p.m, p.n, r->r.key, cx});
             } else {
-                r->mem = nullptr;
+                r->A = static_cast<const double *>(p.A);
+                r->B = static_cast<double *>(p.B);
+                r->lda = p.lda;
+                r->ldb = p.ldb;
             }
-        } else {
-            r->A = static_cast<const double *>(p.A);
-            r->B = static_cast<double *>(p.B);
-            r->lda = p.lda;
-            r->ldb = p.ldb;
+            run.push_back(r);
         }
-        if (st != HSMA_SUCCESS) {
-            std::lock_guard<std::mutex> lk(q->mu);
-            finish(q, r, clock_ns(), st);
-            continue;
+        if (blk && blk->refs == 0) {
+            if (blk->mem) (void)ws_free(blk->mem, s);
+            delete blk;
         }
-        if (p.m <= 64) {
-            hsma_problem sp = p;
+        if (run.empty()) continue;
+        std::vector<hsma_problem> probs;
+        probs.reserve(run.size());
+        for (Req *r : run) {
+            hsma_problem sp = r->r.prob;
             sp.A = r->A;
             sp.B = r->B;
             sp.lda = r->lda;
             sp.ldb = r->ldb;
-            small_probs.push_back(sp);
-            small.push_back(r);
-            r->path = 1;
-            continue;
+            probs.push_back(sp);
         }
-        const double al[2] = {p.alpha_re, p.alpha_im};
-        r->path = 2;
-        st = hsma_trsm((hsma_diag)p.diag, p.m, p.n, al, r->A, r->lda, r->B, r->ldb,
-                       (hsma_dtype)p.dtype, s);
+        hsma_status st = gen_inputs_grouped(gen.data(), (int)gen.size(), s);
+        if (st == HSMA_SUCCESS) st = hsma_trsm_batched(probs.data(), (int64_t)probs.size(), nullptr, s);
         Inflight f;
-        f.reqs.push_back(r);
+        f.reqs = run;
         if (st == HSMA_SUCCESS) {
             hipError_t e = hipEventCreateWithFlags(&f.ev, hipEventDisableTiming);
             if (e == hipSuccess) e = hipEventRecord(f.ev, s);
             if (e != hipSuccess) st = hip_fail(e);
         }
-        if (st != HSMA_SUCCESS) (void)hipStreamSynchronize(s);  // generator may still use r->mem
+        if (st != HSMA_SUCCESS) (void)hipStreamSynchronize(s);  // work already enqueued may use r->mem
         std::lock_guard<std::mutex> lk(q->mu);
         if (st == HSMA_SUCCESS) {
             q->inflight.push_back(f);
         } else {
             if (f.ev) (void)hipEventDestroy(f.ev);
-            finish(q, r, clock_ns(), st);
+            for (Req *r : run) finish(q, r, clock_ns(), st);
         }
-    }
-    if (small.empty()) return;
-    hsma_status st = hsma_trsm_batched(small_probs.data(), (int64_t)small_probs.size(), nullptr,
-                                       q->small_stream);
-    Inflight f;
-    f.reqs = small;
-    if (st == HSMA_SUCCESS) {
-        hipError_t e = hipEventCreateWithFlags(&f.ev, hipEventDisableTiming);
-        if (e == hipSuccess) e = hipEventRecord(f.ev, q->small_stream);
-        if (e != hipSuccess) st = hip_fail(e);
-    }
-    if (st != HSMA_SUCCESS) (void)hipStreamSynchronize(q->small_stream);
-    std::lock_guard<std::mutex> lk(q->mu);
-    if (st == HSMA_SUCCESS) {
-        q->inflight.push_back(f);
-    } else {
-        if (f.ev) (void)hipEventDestroy(f.ev);
-        for (Req *r : small) finish(q, r, clock_ns(), st);
     }
 }
 
-// Simulation backend: streams run their launches one after another; a launch
-// takes sim_fixed_ns + flops / sim_flops_per_ns.  The small requests of one
-// round form one launch on the small stream lasting as long as its largest.
+// Simulation backend: the same size classes and stream assignment; streams
+// run their launches one after another, and a class launch takes
+// sim_fixed_ns + (its summed flops) / sim_flops_per_ns, flops = m^2 n (x4
+// for complex).
 void launch_simulated(hsma_queue *q, std::vector<Req *> &adm) {
     const double now = clock_ns();
     std::lock_guard<std::mutex> lk(q->mu);
     const size_t n_big = (size_t)q->cfg.n_streams;
-    double small_ns = 0;
-    Inflight sm;
+    Inflight f[kClasses];
+    double fl[kClasses] = {};
     for (Req *r : adm) {
         const hsma_problem &p = r->r.prob;
-        const double fl = (double)p.m * p.m * p.n * (p.dtype == HSMA_C64F ? 4.0 : 1.0);
-        const double dur = q->cfg.sim_fixed_ns + fl / q->cfg.sim_flops_per_ns;
-        if (p.m <= 64) {
-            small_ns = std::max(small_ns, dur);
-            sm.reqs.push_back(r);
-            r->path = 1;
-        } else {
-            double &free_at = q->sim_free_at[q->rr++ % n_big];
-            free_at = std::max(free_at, now) + dur;
-            Inflight f;
-            f.t_model_done = free_at;
-            f.reqs.push_back(r);
-            r->path = 2;
-            q->inflight.push_back(f);
-        }
+        const int c = size_class(p);
+        fl[c] += (double)p.m * p.m * p.n * (p.dtype == HSMA_C64F ? 4.0 : 1.0);
+        f[c].reqs.push_back(r);
+        r->path = p.m <= 64 ? 1 : 2;
     }
-    if (!sm.reqs.empty()) {
-        double &free_at = q->sim_free_at[n_big];
-        free_at = std::max(free_at, now) + small_ns;
-        sm.t_model_done = free_at;
-        q->inflight.push_back(sm);
+    for (int c = 0; c < kClasses; ++c) {
+        if (f[c].reqs.empty()) continue;
+        double &free_at = c == 0 ? q->sim_free_at[n_big] : q->sim_free_at[q->rr++ % n_big];
+        free_at = std::max(free_at, now) + q->cfg.sim_fixed_ns + fl[c] / q->cfg.sim_flops_per_ns;
+        f[c].t_model_done = free_at;
+        q->inflight.push_back(f[c]);
     }
 }
 
@@ -294,6 +338,7 @@ void scheduler(hsma_queue *q) {
             }
         }
         if (retired) q->cv_done.notify_all();
+        free_deferred(q, lk);
         // 2. admission, strictly in arrival order
         std::vector<Req *> adm;
         while (!q->pending.empty() && q->n_inflight < q->cfg.max_inflight) {
@@ -311,9 +356,13 @@ void scheduler(hsma_queue *q) {
         }
         if (!adm.empty()) {
             lk.unlock();
+            const double t0 = clock_ns();
             if (hip) launch_admitted(q, adm);
             else launch_simulated(q, adm);
+            const double t1 = clock_ns();
             lk.lock();
+            q->rounds++;
+            q->launch_ns += t1 - t0;
             continue;
         }
         if (q->closing && q->inflight.empty()) {
@@ -498,10 +547,14 @@ hsma_status hsma_queue_release(hsma_queue *q, uint64_t ticket) {
         if (it == q->all.end()) return HSMA_NOT_FOUND;
         hsma::Req *r = it->second;
         if (r->state != hsma::DONE && r->state != hsma::FAILED) return HSMA_PENDING;
-        hsma::free_mem(r);
+        hsma::release_mem(q, r);
         q->budget_used -= r->held;
         q->all.erase(it);
         delete r;
+    }
+    {
+        std::unique_lock<std::mutex> lk(q->mu);
+        hsma::free_deferred(q, lk);
     }
     q->cv_sched.notify_one();
     return HSMA_SUCCESS;
@@ -519,6 +572,8 @@ hsma_status hsma_queue_stats(hsma_queue *q, hsma_queue_statistics *st) {
     st->inflight = q->n_inflight;
     st->bytes_in_use = q->budget_used;
     st->bytes_peak = q->budget_peak;
+    st->rounds = q->rounds;
+    st->launch_ms = q->launch_ns * 1e-6;
     if (!q->latencies_ns.empty()) {
         std::vector<double> v = q->latencies_ns;
         std::sort(v.begin(), v.end());
@@ -543,9 +598,13 @@ hsma_status hsma_queue_destroy(hsma_queue *q) {
     }
     q->cv_sched.notify_one();
     if (q->sched.joinable()) q->sched.join();
-    for (auto &kv : q->all) {
-        hsma::free_mem(kv.second);
-        delete kv.second;
+    {
+        std::unique_lock<std::mutex> lk(q->mu);
+        for (auto &kv : q->all) {
+            hsma::release_mem(q, kv.second);
+            delete kv.second;
+        }
+        hsma::free_deferred(q, lk);
     }
     for (auto s : q->streams) (void)hipStreamSynchronize(s);
     if (q->small_stream) (void)hipStreamSynchronize(q->small_stream);

@@ -58,7 +58,34 @@ hsma_status inv_t(int m, int base, int ib, const double *A, int64_t lda, double 
     return HSMA_SUCCESS;
 }
 
+template <bool UNIT>
+hsma_status inv_group_t(int base, const void *items, int count, hipStream_t s) {
+    const InvItem *it = static_cast<const InvItem *>(items);
+    switch (base / 8) {
+#define HSMA_CASE(N)                                                                              \
+    case N:                                                                                       \
+        hipLaunchKernelGGL((hsma_diag_inv_group<false, N, UNIT>), dim3((unsigned)count), dim3(64), \
+                           0, s, it);                                                             \
+        break;
+        HSMA_CASE(1) HSMA_CASE(2) HSMA_CASE(4) HSMA_CASE(8)
+#undef HSMA_CASE
+        default:
+            return HSMA_INVALID_SIZE;
+    }
+    HSMA_HIP(hipGetLastError());
+    return HSMA_SUCCESS;
+}
+
 }  // namespace
+
+// Grouped diagonal-chunk inversion: `count` InvItems (device memory), all
+// with chunk bound `base` (8, 16, 32 or 64).
+hsma_status launch_inv_group_d(bool unit, int base, const void *items, int count, hipStream_t s) {
+    if (count <= 0) return HSMA_SUCCESS;
+    return unit ? inv_group_t<true>(base, items, count, s) : inv_group_t<false>(base, items, count, s);
+}
+
+size_t inv_item_bytes_d() { return sizeof(InvItem); }
 
 hsma_status launch_small_d(bool unit, int m, int64_t n, cplx alpha, const double *A,
                               int64_t lda, double *B, int64_t ldb, hipStream_t s) {

@@ -354,5 +354,22 @@ __global__ __launch_bounds__(64) void hsma_diag_inv_base(const double *__restric
     Panel<CX, 8 * NCH, UNIT>::template solve<true>(Ad, lda, Wd, ib, mb, mb, cplx{1.0, 0.0});
 }
 
+// The same for many matrices in one launch: workgroup b inverts the chunk
+// described by items[b] (its diagonal chunk of L and where its inverse goes
+// in that matrix's workspace, leading dimension ldw).
+struct InvItem {
+    const double *A;
+    int64_t lda;
+    double *W;
+    int32_t ldw, mb;
+};
+
+template <bool CX, int NCH, bool UNIT>
+__global__ __launch_bounds__(64) void hsma_diag_inv_group(const InvItem *__restrict__ items) {
+    const InvItem d = items[blockIdx.x];
+    Panel<CX, 8 * NCH, UNIT>::template solve<true>(d.A, d.lda, d.W, d.ldw, d.mb, d.mb,
+                                                    cplx{1.0, 0.0});
+}
+
 }  // namespace smallk
 }  // namespace hsma

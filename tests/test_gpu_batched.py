@@ -119,3 +119,36 @@ def test_batched_rejects_bad_descriptor_before_enqueue():
     torch.cuda.synchronize()
     for (_, B, _, _), b0 in zip(dev, before):
         assert np.array_equal(hs.from_colmajor(B), b0, equal_nan=True)
+
+
+def test_grouped_blocked_bitwise_equal_to_single():
+    """Problems with m > 64 in one batch share grouped launches (every
+    problem keeps its own schedule): each result must be bit for bit the
+    single-call result, across data types, diagonal kinds, ragged m, I_B
+    values from the table and alpha = 0."""
+    rng = np.random.default_rng(11)
+    shapes = [(65, 1), (66, 130), (100, 7), (127, 64), (128, 128), (129, 33), (200, 200),
+              (255, 17), (256, 300), (300, 65), (511, 40), (512, 512), (777, 91), (1024, 8),
+              (1100, 260), (1500, 100), (2048, 33), (4100, 20)]
+    probs = []
+    for i, (m, n) in enumerate(shapes):
+        for cx in (False, True):
+            L, B = W.problem(5000 + 2 * i + cx, m, n, cx)
+            unit = (i + cx) % 4 == 3
+            a = complex(rng.uniform(-2, 2), rng.uniform(-1, 1)) if cx else float(rng.uniform(-2, 2))
+            if i == 5:
+                a = 0.0
+            probs.append((L, B, a, unit))
+    dev = to_dev(probs)
+    hs.trsm_batched(dev)
+    torch.cuda.synchronize()
+    dev1 = to_dev(probs)
+    for L, B, a, u in dev1:
+        hs.trsm(L, B, a, unit=u)
+    torch.cuda.synchronize()
+    for k, ((L, B, a, u), (_, Bd, _, _), (_, Bs, _, _)) in enumerate(zip(probs, dev, dev1)):
+        X = hs.from_colmajor(Bd)
+        assert X.tobytes() == hs.from_colmajor(Bs).tobytes(), f"problem {k} {B.shape}"
+        if B.shape[0] <= 1100:
+            ref = oracle.solve(L, B, a, unit=u)
+            assert oracle.rel_err_fro(X, ref) <= 1e-12
