@@ -292,8 +292,9 @@ hsma_status hsma_generate_inputs(hsma_dtype dtype, int64_t m, int64_t n, uint64_
  *   - admits pending requests strictly in arrival order while the HBM budget
  *     and the in-flight limit allow,
  *   - launches each admission round by size class (m <= 64; 64 < m <= 512;
- *     m > 512), each class as one hsma_trsm_batched call with its own
- *     completion event: the small class on the queue's small stream, the two
+ *     m > 512), each class as one batched solve (hsma_trsm_batched's work,
+ *     all of it on the class's stream) with its own completion event: the
+ *     small class on the queue's small stream, the two
  *     blocked classes round-robin over the queue's other streams.  Synthetic
  *     inputs of a class are drawn in one launch on the class's stream first.
  * A request's footprint is its blocked-path workspace (a 4 KiB descriptor
@@ -309,7 +310,7 @@ typedef struct {
                                  of modelled time on its stream (flops = m^2 n,
                                  x4 for complex); for tests of the policy */
     int32_t n_streams;        /* streams for large requests (0 = 4) */
-    int32_t max_inflight;     /* admitted, unfinished requests (0 = 1024) */
+    int32_t max_inflight;     /* admitted, unfinished requests (0 = 8192) */
     int32_t poll_us;          /* completion poll period while work runs (0 = 20) */
     uint64_t hbm_budget_bytes;/* summed footprint limit (0 = 32 GiB) */
     double sim_flops_per_ns;  /* simulated rate (<= 0: 40000, i.e. 40 TFLOP/s) */

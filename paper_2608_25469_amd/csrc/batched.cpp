@@ -191,8 +191,9 @@ static hsma_status run_large(const std::vector<hsma_problem> &large, hipStream_t
     return grouped_blocked(grouped.data(), (int64_t)grouped.size(), s);
 }
 
-// Enqueue the grouped launches (and the large problems) on stream s.
-static hsma_status run_table(const BatchTable &t, hipStream_t s) {
+// Enqueue the grouped launches (and the large problems) on stream s; with
+// fork, the launches are spread over library streams and joined back.
+static hsma_status run_table(const BatchTable &t, hipStream_t s, bool fork = true) {
     DevicePool *pool;
     int cus = 0;
     HSMA_TRY(pool_for(&pool, &cus));
@@ -209,7 +210,7 @@ static hsma_status run_table(const BatchTable &t, hipStream_t s) {
         // Largest-row groups first: they hold the longest items.
         for (int g = kGroups - 1; g >= 0 && st == HSMA_SUCCESS; --g) {
             if (t.count[g] == 0) continue;
-            hipStream_t fs = ngroups == 1 ? s : pool->fork[k++ % kForkStreams];
+            hipStream_t fs = (ngroups == 1 || !fork) ? s : pool->fork[k++ % kForkStreams];
             if (fs != s) HSMA_HIP(hipStreamWaitEvent(fs, fork_ev, 0));
             const bool cx = g >= 16, unit = (g / 8) % 2;
             const int nch = g % 8 + 1;
@@ -231,7 +232,7 @@ static hsma_status run_table(const BatchTable &t, hipStream_t s) {
         }
         // The large problems run beside the small groups.
         if (st == HSMA_SUCCESS && !t.large.empty()) {
-            hipStream_t fs = ngroups == 1 ? s : pool->fork[k++ % kForkStreams];
+            hipStream_t fs = (ngroups == 1 || !fork) ? s : pool->fork[k++ % kForkStreams];
             if (fs != s) HSMA_HIP(hipStreamWaitEvent(fs, fork_ev, 0));
             st = run_large(t.large, fs);
             if (fs != s) {
@@ -303,6 +304,27 @@ hsma_status upload_async(const void *host, size_t bytes, void *dev, hipStream_t 
 
 static hsma_status upload(const std::vector<unsigned char> &img, void *dev, hipStream_t s) {
     return upload_async(img.data(), img.size(), dev, s);
+}
+
+// hsma_trsm_batched with every launch on s itself (no fork onto library
+// streams): for callers that run several batches side by side on their own
+// streams, such as the serving queue.
+hsma_status trsm_batched_serial(const hsma_problem *probs, int64_t count, hipStream_t s) {
+    HSMA_TRY(check_all(probs, count, nullptr));
+    if (count == 0) return HSMA_SUCCESS;
+    if (small_item_bytes_d() != sizeof(Item)) return HSMA_NOT_SUPPORTED;
+    BatchTable t;
+    std::vector<unsigned char> img;
+    build_image(probs, count, &t, &img);
+    if (img.size() > kHeader) {
+        HSMA_TRY(ws_alloc(&t.dev, img.size(), s));
+        t.bytes = img.size();
+        hsma_status st = upload(img, t.dev, s);
+        if (st == HSMA_SUCCESS) st = run_table(t, s, false);
+        hsma_status st2 = ws_free(t.dev, s);
+        return st != HSMA_SUCCESS ? st : st2;
+    }
+    return run_table(t, s, false);
 }
 
 }  // namespace hsma

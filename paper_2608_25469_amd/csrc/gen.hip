@@ -51,6 +51,15 @@ __device__ __forceinline__ void uniforms(uint64_t e, uint32_t tag, uint64_t key,
 __device__ __forceinline__ void gen_l(int cx, int64_t m, uint64_t key, double *__restrict__ L,
                                       int64_t i, int64_t j) {
     const int64_t t = i + j * m;
+    if (i < j) {  // upper triangle: zero, no draw needed
+        if (cx) {
+            L[2 * t] = 0.0;
+            L[2 * t + 1] = 0.0;
+        } else {
+            L[t] = 0.0;
+        }
+        return;
+    }
     double u1, u2;
     uniforms((uint64_t)t, 0u, key, &u1, &u2);
     double re, im;

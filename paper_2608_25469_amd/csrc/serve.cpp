@@ -39,6 +39,7 @@ size_t blocked_workspace_bytes(bool cx, int64_t m, int ib);
 int lookup_block_size(bool cx, int64_t m, int64_t n);
 hsma_status validate(int diag, int dtype, int64_t m, int64_t n, const void *alpha, const void *A,
                      int64_t lda, const void *B, int64_t ldb, bool *quick);
+hsma_status trsm_batched_serial(const hsma_problem *probs, int64_t count, hipStream_t s);
 
 namespace {
 
@@ -259,7 +260,7 @@ void launch_admitted(hsma_queue *q, std::vector<Req *> &adm) {
             probs.push_back(sp);
         }
         hsma_status st = gen_inputs_grouped(gen.data(), (int)gen.size(), s);
-        if (st == HSMA_SUCCESS) st = hsma_trsm_batched(probs.data(), (int64_t)probs.size(), nullptr, s);
+        if (st == HSMA_SUCCESS) st = trsm_batched_serial(probs.data(), (int64_t)probs.size(), s);
         Inflight f;
         f.reqs = run;
         if (st == HSMA_SUCCESS) {
@@ -430,7 +431,7 @@ hsma_status hsma_queue_create(const hsma_queue_config *cfg, hsma_queue **out) {
     if (c.max_inflight < 0 || c.n_streams < 0 || c.poll_us < 0 || c.sim_fixed_ns < 0)
         return HSMA_INVALID_VALUE;
     if (c.hbm_budget_bytes == 0) c.hbm_budget_bytes = (uint64_t)32 << 30;
-    if (c.max_inflight == 0) c.max_inflight = 1024;
+    if (c.max_inflight == 0) c.max_inflight = 8192;
     if (c.n_streams == 0) c.n_streams = 4;
     if (c.poll_us == 0) c.poll_us = 20;
     if (!(c.sim_flops_per_ns > 0)) c.sim_flops_per_ns = 40000.0;

@@ -4,21 +4,22 @@
 // separate forward substitution; the triangular operand is shared.  Here one
 // 64-lane wavefront owns a panel of up to 64 columns: lane j keeps column j
 // of the panel entirely in VGPRs (y[0..m-1]), so the row-dependency chain runs
-// inside a lane with no synchronisation at all.  L is the same for every lane,
-// so it is read through the scalar data cache into SGPRs (address space 4),
-// which costs no vector-memory or LDS bandwidth and feeds v_fma_f64 directly as
-// its scalar operand.
+// inside a lane with no synchronisation at all.
 //
-// The loop nest is fully unrolled for a compile-time row bound MAXM and
-// guarded by the runtime m at 8-row granularity.  Rows are processed in blocks
-// of 8 in left-looking order: block R first receives the updates of every
-// finished block K < R (8x8 multiply-adds per column of L, one 64-byte scalar
-// load per 8 coefficients), then its own 8x8 triangle is solved and each row
-// is written back the moment it is final.  The loads of B are all issued up
-// front and the waits count down row by row, so global loads of later rows
-// overlap the dependency chain of earlier ones and stores trail it (the
-// load/compute/store overlap of Sec. 4.2.1, Alg. 1, realised by full unrolling
-// plus the hardware's in-order vmcnt waits).
+// L is the same for every lane.  Its packed lower triangle is staged once in
+// LDS with direct global-to-LDS loads (no VGPR round trip).  At step k,
+// column k+1 is read from LDS into ceil(m/16) VGPRs laid out so that each
+// 16-lane row of the wavefront holds 16 consecutive rows of the column, and
+// each coefficient reaches all lanes through the 64-bit DPP row_newbcast
+// broadcast, which feeds v_fma_f64 with no further memory traffic.  The
+// column for the next step is read before the current step's arithmetic, so
+// LDS latency hides behind the dependency chain.
+//
+// The loop nest is fully unrolled for a compile-time row bound MAXM (a
+// multiple of 8) and guarded by the runtime m; all loads of B are issued up
+// front and every row is stored as soon as the panel is final, so global
+// traffic overlaps the chain (the load/compute/store overlap of Sec. 4.2.1,
+// Alg. 1, obtained by full unrolling and the hardware's in-order waits).
 //
 // Reciprocals of the diagonal are computed once per wavefront, one per lane,
 // and broadcast to the whole wave with v_readlane when row k is divided.
