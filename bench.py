@@ -1,18 +1,20 @@
 #!/usr/bin/env python3
 """Throughput benchmark of the gfx950 TRSM library.
 
-Default workload (large_real): one real solve, m = n = 16384, FP64,
-alpha = -1, non-unit L with l_ij ~ U(-1,1)/m below the diagonal and
-l_ii ~ U(1,2), B ~ N(0,1), seed 2 -- the configuration the FP64-peak target is
-stated on.  A "step" is one complete solve through the blocked path
-(diagonal-block inversion, recursive matrix-core updates, in-place diagonal
-solves) with inputs resident in HBM; every step re-solves B in place.
+Default (no --workload): the batched configuration -- 10 000 independent
+double-complex solves, m, n ~ U{8..64}, alpha = (1, 0.5), seed 1, one step =
+the whole batch with descriptors resident in HBM (hsma_batch_plan_execute).
+`value` is solves/s; the roofline is that of the grouped small-solve kernel
+(HBM-bound).  The same JSON line carries the other parts of the headline
+metric, each measured in this run: DTRSM m = n = 16384 and ZTRSM
+m = n = 8192 (GFLOP/s, % of FP64 peak, roofline of the trailing-update
+kernel, rocBLAS on the same GPU) and the serving run (p50/p99 latency,
+solves/s) -- under "headline".
 
-Other workloads (--workload):
+Single workloads (--workload):
+  large_real     DTRSM m = n = 16384, alpha = -1, seed 2 (one step = one solve)
   large_complex  ZTRSM m = n = 8192, alpha = (-1, 0), seed 2
-  batched        10 000 independent complex solves, m, n ~ U{8..64},
-                 alpha = (1, 0.5), seed 1 (one step = the whole batch,
-                 descriptors resident: hsma_batch_plan_execute)
+  batched        the default configuration alone
   single         DTRSM m = n = 32, alpha = 1, seed 0
   mixed          DTRSM m = 8192, n = 4096: mixed precision vs FP64 at equal
                  backward error, kappa(L) ~ 1e3 .. 1e6, seed 3
@@ -22,9 +24,9 @@ Other workloads (--workload):
                  Philox keys, 32 GiB budget; reports p50/p99 latency from
                  scheduled arrival to completion and solves/s
 
-Prints one JSON line: metric/value (GFLOP/s), the roofline of the dominant
-kernel measured with HIP events on its launch stream, rocBLAS on the same GPU
-and inputs, and the CPU oracle timed on a bounded sample of the same work.
+Prints one JSON line: metric/value, the roofline of the dominant kernel
+measured with HIP events on its launch stream, rocBLAS on the same GPU and
+inputs, and the CPU oracle timed on a bounded sample of the same work.
 """
 from __future__ import annotations
 
@@ -52,8 +54,9 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="large_real",
-                    choices=["large_real", "large_complex", "batched", "single", "mixed", "serving"])
+    ap.add_argument("--workload", default="default",
+                    choices=["default", "large_real", "large_complex", "batched", "single", "mixed",
+                             "serving"])
     ap.add_argument("--ib", type=int, default=0, help="force I_B (0 = tuning table)")
     ap.add_argument("--m", type=int, default=0, help="override m (and n) for sweeps")
     ap.add_argument("--n", type=int, default=0)
@@ -66,6 +69,8 @@ def parse():
     ap.add_argument("--rate", type=float, default=20000.0, help="serving: arrivals per second")
     ap.add_argument("--duration", type=float, default=12.0, help="serving: seconds of arrivals")
     ap.add_argument("--streams", type=int, default=0, help="serving: queue streams (0 = default)")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="fill a 1 GiB tensor and copy it first (reference kernels of known size for counter runs)")
     return ap.parse_args()
 
 
@@ -106,23 +111,30 @@ class RocBlas:
             raise RuntimeError(f"rocblas trsm: {st}")
 
 
-def measured_traffic(workload, m, n, ib):
-    """HBM bytes per update launch from the committed rocprofv3 FETCH/WRITE
-    measurement, if it was taken on this workload and on the current kernel
-    source; otherwise None."""
+def measured_traffic(name, sources, ok=True):
+    """HBM bytes per launch of a kernel from a committed rocprofv3
+    FETCH_SIZE/WRITE_SIZE measurement (profiles/<name>.json), if it was taken
+    on the current kernel sources; otherwise None."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "gemm_update_dtrsm16384_traffic.json")
+    if not ok:
+        return None
     try:
-        import json as _json
-        rec = _json.load(open(path))
-        src = open(os.path.join(ROOT, rec["source"]), "rb").read()
-    except (OSError, ValueError, KeyError):
+        rec = json.load(open(os.path.join(ROOT, "profiles", name + ".json")))
+    except (OSError, ValueError):
         return None
-    if hashlib.sha256(src).hexdigest() != rec.get("source_sha256"):
+    h = hashlib.sha256()
+    for src in sources:
+        try:
+            h.update(open(os.path.join(ROOT, src), "rb").read())
+        except OSError:
+            return None
+    if h.hexdigest() != rec.get("source_sha256"):
         return None
-    if workload != "large_real" or (m, n) != (16384, 16384) or ib not in (0, 256):
-        return None
-    return rec["hbm_bytes_per_launch"]
+    return rec.get("hbm_bytes_per_launch")
+
+
+GEMM_SOURCES = ["paper_2608_25469_amd/csrc/gemm.hip"]
+SMALL_SOURCES = ["paper_2608_25469_amd/csrc/small_kernels.h", "paper_2608_25469_amd/csrc/small_z.hip"]
 
 
 def time_gpu(fn, steps, warmup, torch):
@@ -210,7 +222,8 @@ def run_single_problem(args, torch, hs, cfg):
         ach = (up["flops"] / up["launches"]) / (avg * 1e-3) / 1e12
         roof = {"bound": "mfma", "kernel": "hsma_gemm (trailing-update role)", "achieved": round(ach, 3),
                 "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": round(ach / FP64_PEAK_TFLOPS, 4),
-                "traffic": measured_traffic(args.workload, m, n, args.ib),
+                "traffic": measured_traffic("gemm_update_dtrsm16384_traffic", GEMM_SOURCES,
+                                            (m, n, cx, args.ib) == (16384, 16384, False, 0)),
                 "avg_launch_ms": avg, "launches_per_step": up["launches"] // args.steps,
                 "flops_per_launch": up["flops"] / up["launches"],
                 "per_unit": "2 flops per real multiply-add of C -= A B (complex: its real expansion)"}
@@ -301,13 +314,22 @@ def run_batched(args, torch, hs, cfg):
     fl = b.total_flops()
     byts = b.total_bytes()
     sm = prof["small"]
+    launches = max(1, sm["launches"] // args.steps)
+    avg_launch_ms = sm["ms"] / max(1, sm["launches"])
+    bytes_per_launch = byts / launches
+    ach = bytes_per_launch / (avg_launch_ms * 1e-3) / 1e9
+    traffic = measured_traffic("small_solve_batched10000_traffic", SMALL_SOURCES, count == cfg["count"])
     roof = {"bound": "hbm", "kernel": "hsma_small_solve (grouped, persistent)",
-            "achieved": round(byts / (ev_ms * 1e-3) / 1e9, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(byts / (ev_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4), "traffic": None,
-            "bytes_per_step": byts, "event_ms_per_step": ev_ms,
-            "group_launches_per_step": sm["launches"] // args.steps,
-            "mean_group_launch_ms": sm["ms"] / max(1, sm["launches"]),
-            "per_unit": "per problem: lower triangle of L once, B read and written once"}
+            "achieved": round(ach, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic,
+            "avg_launch_ms": avg_launch_ms, "launches_per_step": launches,
+            "bytes_per_launch": bytes_per_launch, "bytes_per_step": byts,
+            "step_ms_events": ev_ms,
+            "step_rate_gbs": round(byts / (ev_ms * 1e-3) / 1e9, 2),
+            "per_unit": "per problem: 16 (m(m+1)/2 + 2mn) bytes (lower triangle of L once, B read and "
+                        "written once); a launch serves one (dtype, diag, ceil(m/8)) group, so bytes per "
+                        "launch = bytes per step / group launches per step; launches of one step run "
+                        "concurrently on separate streams"}
 
     # One-shot API (host descriptors uploaded each call) for reference.
     oneshot_ms = time_gpu(lambda: hs.trsm_batched(probs), max(2, args.steps), 1, torch)
@@ -346,10 +368,11 @@ def run_batched(args, torch, hs, cfg):
         if done == count:
             cpu["sample"] = f"all {count} problems"
     plan.close()
-    value = fl / (ms * 1e-3) / 1e9
+    gflops = fl / (ms * 1e-3) / 1e9
     return {
-        "value": round(value, 2), "unit": "GFLOP/s", "ms_per_step": round(ms, 4), "dtype": "c128",
-        "pct_fp64_peak": round(100 * value / (FP64_PEAK_TFLOPS * 1e3), 3),
+        "value": round(count / (ms * 1e-3), 1), "unit": "solves/s", "ms_per_step": round(ms, 4),
+        "dtype": "c128", "gflops": round(gflops, 2),
+        "pct_fp64_peak": round(100 * gflops / (FP64_PEAK_TFLOPS * 1e3), 3),
         "solves_per_s": round(count / (ms * 1e-3), 1),
         "extra_config": {"count": count, "flops_per_step": fl, "bytes_per_step": byts,
                          "oneshot_ms_per_call": round(oneshot_ms, 4)},
@@ -559,6 +582,38 @@ def run_serving(args, torch, hs):
     }
 
 
+def run_headline(args, torch, hs, names):
+    """The rest of the headline metric in the same run: the large DTRSM and
+    ZTRSM solves and the serving run (each failure is reported, not fatal)."""
+    import copy
+    out = {}
+    sub = copy.copy(args)
+    sub.no_cpu_baseline = True
+    sub.steps, sub.warmup = 3, 1
+    for key in ("large_real", "large_complex"):
+        cfg = dict({"large_real": W.LARGE_REAL, "large_complex": W.LARGE_COMPLEX}[key])
+        sub.workload = key
+        try:
+            r = run_single_problem(sub, torch, hs, cfg)
+            out[key] = {"workload": names[key], "gflops": r["value"], "pct_fp64_peak": r["pct_fp64_peak"],
+                        "ms_per_solve": r["ms_per_step"], "roofline": r.get("roofline"),
+                        "rocblas": r.get("rocblas"), "parity": r.get("parity"),
+                        "phases": r.get("phases")}
+        except Exception as e:  # reported in the line
+            out[key] = {"error": repr(e)}
+        torch.cuda.empty_cache()
+        hs.workspace_release()
+    try:
+        sub.workload = "serving"
+        r = run_serving(sub, torch, hs)
+        out["serving"] = dict(r["serving"], solves_per_s=r["solves_per_s"], parity=r.get("parity"),
+                              workload=f"Poisson {sub.rate:.0f} req/s for {sub.duration:.0f} s, "
+                                       "m log-U[8,4096], n log-U[1,512], 30% complex, seed 4")
+    except Exception as e:
+        out["serving"] = {"error": repr(e)}
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -573,11 +628,25 @@ def main():
     torch.cuda.set_device(0)
     hs.lib()
 
+    if args.calibrate_copy:
+        # A plain device copy of known size (1 GiB read, 1 GiB written): the
+        # reference that rocprofv3's FETCH_SIZE / WRITE_SIZE are scaled by.
+        src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
     names = {"large_real": "DTRSM left-lower, m=n=16384, FP64, alpha=-1, seed 2",
              "large_complex": "ZTRSM left-lower, m=n=8192, complex FP64, alpha=(-1,0), seed 2",
              "batched": "ZTRSM batched: 10000 solves, m,n ~ U{8..64}, alpha=(1,0.5), seed 1",
              "single": "DTRSM left-lower, m=n=32, FP64, alpha=1, seed 0"}
-    if args.workload == "mixed":
+    headline = None
+    if args.workload == "default":
+        res = run_batched(args, torch, hs, dict(W.BATCHED))
+        workload = names["batched"]
+        headline = run_headline(args, torch, hs, names)
+    elif args.workload == "mixed":
         res = run_mixed(args, torch, hs, dict(W.MIXED))
         workload = "DTRSM mixed precision vs FP64, m=8192, n=4096, kappa_inf ~1e3..1e6, seed 3"
     elif args.workload == "serving":
@@ -605,10 +674,12 @@ def main():
         "config": dict({"workload": workload, "parallelism": "single GPU",
                         "flop_convention": "real m^2 n; complex 4 m^2 n + 2 m n"}, **res["extra_config"]),
     }
-    for k in ("solves_per_s", "phases", "parity", "roofline", "rocblas", "cpu_baseline", "mixed",
-              "serving"):
+    for k in ("solves_per_s", "gflops", "phases", "parity", "roofline", "rocblas", "cpu_baseline",
+              "mixed", "serving"):
         if k in res:
             out[k] = res[k]
+    if headline is not None:
+        out["headline"] = headline
     print(json.dumps(out), flush=True)
 
 
