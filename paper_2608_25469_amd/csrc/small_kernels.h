@@ -53,9 +53,12 @@ struct alignas(16) dpair {
 // are clamped to m-1 (addresses never leave A); the values of rows >= m and
 // of rows on or above the diagonal are never used by an update that matters.
 // ---------------------------------------------------------------------------
+// Every row and bank is enabled, so no lane keeps an old value: mov_dpp
+// (old value undefined) needs no copy of the destination first, unlike
+// update_dpp with a tied old operand.
 template <int N>
 __device__ __forceinline__ double bcast16(double v) {
-    return __builtin_amdgcn_update_dpp(v, v, 0x150 + N, 0xf, 0xf, false);  // row_newbcast:N
+    return __builtin_amdgcn_mov_dpp(v, 0x150 + N, 0xf, 0xf, false);  // row_newbcast:N
 }
 
 template <int R>
@@ -144,7 +147,11 @@ struct Panel {
             // Each column step is its own basic block (K < m is uniform): this
             // keeps the instruction selector from sinking the step's
             // multiply-adds to their final uses, which would keep every
-            // broadcast coefficient of the unrolled body alive at once.
+            // broadcast coefficient of the unrolled body alive at once.  The
+            // next step is nested inside this one's block, so the steps form a
+            // chain with early exits and the row values never pass through a
+            // join per step (which would cost a register copy of every row at
+            // every step).
             if (K < m) {
                 read_col<K + 1>(Ls, lane, nr, ni);
                 if (!UNIT) {
@@ -160,8 +167,8 @@ struct Panel {
                     }
                 }
                 if constexpr (K + 1 < MAXM) ApplyRows<CX, MAXM, K, K + 1>::run(yr, yi, cr, ci, yr[K], yi[K]);
+                step<K + 1>(Ls, m, lane, rr, ri, yr, yi, nr, ni);
             }
-            step<K + 1>(Ls, m, lane, rr, ri, yr, yi, nr, ni);
         }
     }
 
@@ -172,7 +179,12 @@ struct Panel {
     static __device__ __forceinline__ void solve(const double *__restrict__ A, int64_t lda,
                                                  double *__restrict__ B, int64_t ldb, int m,
                                                  int ncols, cplx alpha) {
-        const int lane = threadIdx.x & 63;
+        // The lane id is laundered through an empty asm so that nothing
+        // derived from it (LDS and row indices of every unrolled step) is
+        // hoisted out of the persistent item loop: hoisted, those values
+        // would stay live across the whole kernel and cost occupancy.
+        int lane = threadIdx.x & 63;
+        asm volatile("" : "+v"(lane));
         const bool active = lane < ncols;
         double *__restrict__ bc = B + ES * (int64_t)(active ? lane : 0) * ldb;
 
