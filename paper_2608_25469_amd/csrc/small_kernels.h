@@ -16,8 +16,13 @@
 // LDS latency hides behind the dependency chain.
 //
 // The loop nest is fully unrolled for a compile-time row bound MAXM (a
-// multiple of 8) and guarded by the runtime m; all loads of B are issued up
-// front and every row is stored as soon as the panel is final, so global
+// multiple of 8) and guarded by the runtime m.  Two walks share this
+// machinery: Panel (right-looking, the whole column live; used with identity
+// right-hand sides to invert diagonal chunks) and PanelLL (left-looking over
+// 16-row blocks, used for general right-hand sides: a lane holds one block
+// at a time, so register use no longer grows with m and larger panels keep
+// two or more wavefronts per SIMD).  Loads of a block are issued before its
+// arithmetic and its rows are stored as soon as they are final, so global
 // traffic overlaps the chain (the load/compute/store overlap of Sec. 4.2.1,
 // Alg. 1, obtained by full unrolling and the hardware's in-order waits).
 //
@@ -25,6 +30,8 @@
 // and broadcast to the whole wave with v_readlane when row k is divided.
 
 #pragma once
+
+#include <type_traits>
 
 #include "internal.h"
 
@@ -287,12 +294,242 @@ struct Panel {
     }
 };
 
-template <bool CX, int NCH, bool UNIT>
-__device__ __forceinline__ void solve_panel(const double *__restrict__ A, int64_t lda,
-                                            double *__restrict__ B, int64_t ldb, int m, int ncols,
-                                            cplx alpha) {
-    Panel<CX, 8 * NCH, UNIT>::template solve<false>(A, lda, B, ldb, m, ncols, alpha);
+// ---------------------------------------------------------------------------
+// The same solve walked left-looking over 16-row blocks (used for general
+// right-hand sides; the identity right-hand sides of the diagonal-block
+// inversion keep the right-looking Panel above).
+//
+// Holding a whole column in registers costs 2 m doubles per lane -- for
+// complex m = 64 all 256 architectural VGPRs, so the compiler spills the
+// working set to AGPRs and only one wavefront fits per SIMD.  Here a lane
+// holds one 16-row block of its column (y) plus one finished block (x):
+// block R is loaded, receives the updates of every finished block K < R
+// (whose final values the same lane stored to B earlier and reloads), solves
+// its own 16 x 16 triangle, and is stored.  Every element still receives its
+// updates -l_ik x_k in ascending k, exactly as in the right-looking order, so
+// the results are the same bit for bit.
+// ---------------------------------------------------------------------------
+template <int B, int E, typename F>
+__device__ __forceinline__ void static_for(F &&f) {
+    if constexpr (B < E) {
+        f(std::integral_constant<int, B>{});
+        static_for<B + 1, E>(f);
+    }
 }
+
+template <bool CX, int MAXM, bool UNIT>
+struct PanelLL {
+    static constexpr int RB = 16;
+    static constexpr int NB = (MAXM + RB - 1) / RB;
+    static constexpr int ES = CX ? 2 : 1;
+    // LDS: the 16-row panel of L that block R needs (rows R*16.., columns
+    // 0..R*16+15), column-major with 16 rows per column.
+    static constexpr int PANEL = RB * MAXM;
+
+    // Coefficients l_{R*16 + l%16, k} of column k for the current panel.
+    static __device__ __forceinline__ void coef(const double *Lp, int lane, int k, double &cr,
+                                                double &ci) {
+        const int e = k * RB + (lane & 15);
+        if (CX) {
+            cr = Lp[2 * e];
+            ci = Lp[2 * e + 1];
+        } else {
+            cr = Lp[e];
+            ci = 0.0;
+        }
+    }
+
+    // Stage rows R*16..R*16+15 of columns 0..(R+1)*16-1 (at most MAXM) with
+    // direct global-to-LDS loads.  Complex: one instruction moves 4 columns
+    // (lane l: column 4c + l/16, row l%16, 16 bytes); real: 2 columns (lane
+    // l: column 2c + l/32, row (l%32)/2, 4-byte half l%2).  Source rows are
+    // clamped to [column, m-1] and columns to m-1, so only the lower triangle
+    // of A is read and nothing outside it; rows and columns beyond m only feed
+    // rows that are never stored, and rows on or above the diagonal are never
+    // used.
+    template <int R>
+    static __device__ __forceinline__ void stage(const double *__restrict__ A, int64_t lda, int m,
+                                                 int lane, double *Lp) {
+        typedef __attribute__((address_space(3))) void lds_void;
+        constexpr int NCOL = ((R + 1) * RB) < MAXM ? ((R + 1) * RB) : MAXM;
+        const int mc = m - 1;
+        if (CX) {
+#pragma unroll
+            for (int c = 0; c < NCOL / 4; ++c) {
+                int col = 4 * c + (lane >> 4);
+                col = col < mc ? col : mc;
+                int row = R * RB + (lane & 15);
+                row = row < col ? col : (row < mc ? row : mc);
+                const double *src = A + 2 * ((int64_t)col * lda + row);
+                __builtin_amdgcn_global_load_lds((const void *)src, (lds_void *)(Lp + 2 * (c * 64)), 16, 0,
+                                                 0);
+            }
+        } else {
+#pragma unroll
+            for (int c = 0; c < NCOL / 2; ++c) {
+                int col = 2 * c + (lane >> 5);
+                col = col < mc ? col : mc;
+                int row = R * RB + ((lane & 31) >> 1);
+                row = row < col ? col : (row < mc ? row : mc);
+                const char *src = reinterpret_cast<const char *>(A + (int64_t)col * lda + row) + 4 * (lane & 1);
+                __builtin_amdgcn_global_load_lds((const void *)src, (lds_void *)(Lp + c * 32), 4, 0, 0);
+            }
+        }
+    }
+
+    // Diagonal step KK of block R: x = y[KK] / l_KK, then rows KK+1.. of the
+    // block receive -l_iK x.  c holds column K's coefficients (read one step
+    // earlier); the next column's are read first.  Steps nest so that the
+    // block's row values never pass through a join per step.
+    template <int R, int BR, int KK>
+    static __device__ __forceinline__ void diag_step(const double *Lp, int m, int lane, double rr,
+                                                     double ri, double (&yr)[RB], double (&yi)[RB],
+                                                     double cr, double ci) {
+        if constexpr (KK < BR) {
+            constexpr int K = R * RB + KK;
+            if (K < m) {
+                double nr = 0.0, ni = 0.0;
+                if constexpr (KK + 1 < BR) coef(Lp, lane, K + 1, nr, ni);
+                if (!UNIT) {
+                    const double dr = readlane_d(rr, K);
+                    if (CX) {
+                        const double di = readlane_d(ri, K);
+                        const double tr = yr[KK] * dr - yi[KK] * di;
+                        const double ti = yr[KK] * di + yi[KK] * dr;
+                        yr[KK] = tr;
+                        yi[KK] = ti;
+                    } else {
+                        yr[KK] *= dr;
+                    }
+                }
+                const double xr = yr[KK], xi = yi[KK];
+                static_for<KK + 1, BR>([&](auto I) {
+                    constexpr int i = decltype(I)::value;
+                    const double lr = bcast16<i & 15>(cr);
+                    const double li = CX ? bcast16<i & 15>(ci) : 0.0;
+                    fms<CX>(yr[i], yi[i], lr, li, xr, xi);
+                });
+                diag_step<R, BR, KK + 1>(Lp, m, lane, rr, ri, yr, yi, nr, ni);
+            }
+        }
+    }
+
+    // Block R: stage its panel of L, load, apply finished blocks, solve the
+    // diagonal triangle, store.
+    template <int R>
+    static __device__ __forceinline__ void block(const double *__restrict__ A, int64_t lda,
+                                                 double *Lp, double *__restrict__ bc, bool active,
+                                                 int m, int lane, double rr, double ri, cplx alpha) {
+        if constexpr (R < NB) {
+            constexpr int BR = (MAXM - R * RB) < RB ? (MAXM - R * RB) : RB;  // rows of this block
+            if (R * RB < m) {
+                __syncthreads();  // the previous panel's reads are complete
+                stage<R>(A, lda, m, lane, Lp);
+                double yr[RB], yi[RB];
+#pragma unroll
+                for (int i = 0; i < BR; ++i) {
+                    const int g = R * RB + i;
+                    const int gc = g < m ? g : m - 1;
+                    if (CX) {
+                        const dpair v = reinterpret_cast<const dpair *>(bc)[gc];
+                        yr[i] = v.x;
+                        yi[i] = v.y;
+                    } else {
+                        yr[i] = bc[gc];
+                        yi[i] = 0.0;
+                    }
+                    if (g >= m) yr[i] = yi[i] = 0.0;
+                }
+                if (alpha.re != 1.0 || alpha.im != 0.0) {
+#pragma unroll
+                    for (int i = 0; i < BR; ++i) {
+                        if (CX) {
+                            const double tr = alpha.re * yr[i] - alpha.im * yi[i];
+                            const double ti = alpha.re * yi[i] + alpha.im * yr[i];
+                            yr[i] = tr;
+                            yi[i] = ti;
+                        } else {
+                            yr[i] *= alpha.re;
+                        }
+                    }
+                }
+                __syncthreads();  // the panel has landed in LDS
+                // Updates from the finished blocks, in ascending column order.
+                static_for<0, R>([&](auto KB) {
+                    constexpr int Kb = decltype(KB)::value;
+                    double xr[RB], xi[RB];
+#pragma unroll
+                    for (int k = 0; k < RB; ++k) {
+                        if (CX) {
+                            const dpair v = reinterpret_cast<const dpair *>(bc)[Kb * RB + k];
+                            xr[k] = v.x;
+                            xi[k] = v.y;
+                        } else {
+                            xr[k] = bc[Kb * RB + k];
+                            xi[k] = 0.0;
+                        }
+                    }
+                    double cr, ci;
+                    coef(Lp, lane, Kb * RB, cr, ci);
+                    static_for<0, RB>([&](auto KK) {
+                        constexpr int kk = decltype(KK)::value;
+                        double nr = 0.0, ni = 0.0;
+                        if constexpr (kk + 1 < RB) coef(Lp, lane, Kb * RB + kk + 1, nr, ni);
+                        static_for<0, BR>([&](auto I) {
+                            constexpr int i = decltype(I)::value;
+                            const double lr = bcast16<i & 15>(cr);
+                            const double li = CX ? bcast16<i & 15>(ci) : 0.0;
+                            fms<CX>(yr[i], yi[i], lr, li, xr[kk], xi[kk]);
+                        });
+                        cr = nr;
+                        ci = ni;
+                    });
+                });
+                double cr, ci;
+                coef(Lp, lane, R * RB, cr, ci);
+                diag_step<R, BR, 0>(Lp, m, lane, rr, ri, yr, yi, cr, ci);
+                if (active) {
+#pragma unroll
+                    for (int i = 0; i < BR; ++i) {
+                        if (R * RB + i < m) {
+                            if (CX)
+                                reinterpret_cast<dpair *>(bc)[R * RB + i] = dpair{yr[i], yi[i]};
+                            else
+                                bc[R * RB + i] = yr[i];
+                        }
+                    }
+                }
+                block<R + 1>(A, lda, Lp, bc, active, m, lane, rr, ri, alpha);
+            }
+        }
+    }
+
+    static __device__ __forceinline__ void solve(const double *__restrict__ A, int64_t lda,
+                                                 double *__restrict__ B, int64_t ldb, int m,
+                                                 int ncols, cplx alpha) {
+        // Laundered lane id: see Panel::solve.
+        int lane = threadIdx.x & 63;
+        asm volatile("" : "+v"(lane));
+        const bool active = lane < ncols;
+        double *__restrict__ bc = B + ES * (int64_t)(active ? lane : 0) * ldb;
+
+        double rr = 1.0, ri = 0.0;
+        if (!UNIT && lane < m) {
+            const double *d = A + ES * ((int64_t)lane + (int64_t)lane * lda);
+            if (CX) {
+                const dpair v = *reinterpret_cast<const dpair *>(d);
+                const double den = v.x * v.x + v.y * v.y;
+                rr = v.x / den;
+                ri = -v.y / den;
+            } else {
+                rr = 1.0 / d[0];
+            }
+        }
+        __shared__ double Lp[ES * PANEL];
+        block<0>(A, lda, Lp, bc, active, m, lane, rr, ri, alpha);
+        __syncthreads();  // LDS is reused by the next item of a persistent wave
+    }
+};
 
 // Work item of the small-solve kernel: one 64-column panel of one problem.
 struct SmallItem {
@@ -317,8 +554,15 @@ struct SmallGroup {
 // next item index from the group's counter until the group is exhausted.
 // Items are sorted by decreasing cost on the host, so the longest panels
 // start first.
+// Complex panels of 49..64 rows fit two wavefronts per SIMD (256 registers
+// each) with the left-looking walk; without the hint the compiler spreads
+// into the whole register file for one.
+template <bool CX, int NCH>
+constexpr int small_waves() { return (CX && NCH >= 7) ? 2 : 1; }
+
 template <bool CX, int NCH, bool UNIT>
-__global__ __launch_bounds__(64) void hsma_small_solve(SmallItem one, SmallGroup grp) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(small_waves<CX, NCH>())))
+void hsma_small_solve(SmallItem one, SmallGroup grp) {
     const int lane = threadIdx.x & 63;
     for (int it = 0;; ++it) {
         SmallItem d;
@@ -344,8 +588,7 @@ __global__ __launch_bounds__(64) void hsma_small_solve(SmallItem one, SmallGroup
             }
             continue;
         }
-        Panel<CX, 8 * NCH, UNIT>::template solve<false>(d.A, d.lda, d.B, d.ldb, d.m, d.ncols,
-                                                         cplx{d.ar, d.ai});
+        PanelLL<CX, 8 * NCH, UNIT>::solve(d.A, d.lda, d.B, d.ldb, d.m, d.ncols, cplx{d.ar, d.ai});
     }
 }
 
