@@ -8,7 +8,9 @@ the whole batch with descriptors resident in HBM (hsma_batch_plan_execute).
 (HBM-bound).  The same JSON line carries the other parts of the headline
 metric, each measured in this run: DTRSM m = n = 16384 and ZTRSM
 m = n = 8192 (GFLOP/s, % of FP64 peak, roofline of the trailing-update
-kernel, rocBLAS on the same GPU) and the serving run (p50/p99 latency,
+kernel, rocBLAS on the same GPU), graph replay against eager launches on a
+mid-size blocked solve, the mixed-precision mode against FP64 at equal
+backward error (kappa ~1e3 and ~1e6), and the serving run (p50/p99 latency,
 solves/s) -- under "headline".
 
 Single workloads (--workload):
@@ -380,12 +382,42 @@ def run_batched(args, torch, hs, cfg):
     }
 
 
-def run_mixed(args, torch, hs, cfg):
+def run_graph(args, torch, hs, sizes=(256, 512, 1024), reps=30):
+    """Blocked schedule replayed as a captured HIP graph vs launched eagerly,
+    on mid-size DTRSMs where launch overhead matters (same inputs, results
+    compared bit for bit)."""
+    return [run_graph_one(torch, hs, m, m, reps) for m in sizes]
+
+
+def run_graph_one(torch, hs, m, n, reps):
+    L, B = W.problem(2, m, n, False)
+    Ld, Bd, B0 = hs.to_colmajor(L), hs.to_colmajor(B), hs.to_colmajor(B)
+    out = {}
+    for mode in ("eager", "graph"):
+        g = mode == "graph"
+        Bd.copy_(B0)
+        hs.trsm(Ld, Bd, -1.0, graph=g)
+        torch.cuda.synchronize()
+        X = Bd.clone()
+        t = time.perf_counter()
+        for _ in range(reps):
+            hs.trsm(Ld, Bd, -1.0, graph=g)   # re-solves in place: same work each time
+        torch.cuda.synchronize()
+        out[mode + "_ms"] = (time.perf_counter() - t) * 1e3 / reps
+        out[mode + "_first"] = X
+    same = bool(torch.equal(out.pop("eager_first"), out.pop("graph_first")))
+    hs.graph_cache_clear()
+    return {"workload": f"DTRSM m=n={m}, blocked path", "eager_ms": round(out["eager_ms"], 4),
+            "graph_ms": round(out["graph_ms"], 4), "speedup": round(out["eager_ms"] / out["graph_ms"], 3),
+            "bitwise_equal": same}
+
+
+def run_mixed(args, torch, hs, cfg, kappas=(1e3, 1e4, 1e5, 1e6)):
     """Mixed precision vs plain FP64 at equal backward error (<= 1e-13) on
     m = 8192, n = 4096, for kappa_inf(L) of about 1e3, 1e4, 1e5, 1e6."""
     import oracle
     m, n = (args.m or cfg["m"]), (args.n or cfg["n"])
-    kappas = [1e3, 1e4, 1e5, 1e6]
+    kappas = list(kappas)
     rows = []
     fl = W.flops(m, n, False)
 
@@ -418,6 +450,12 @@ def run_mixed(args, torch, hs, cfg):
                                                    refine_tol=tol, report=True), Bd, Bp, reps)
         # and the mixed solve alone (no refinement), for the kernel-level ratio
         t32, _, _ = timed(lambda: hs.trsm(Ld, Bd, 1.0, mixed=True), Bd, Bp, reps)
+        # one fixed refinement step without the certifying residual (its
+        # backward error is checked by the oracle on sampled columns below)
+        t1s, _, _ = timed(lambda: hs.trsm(Ld, Bd, 1.0, mixed=True, refine_steps=1), Bd, Bp, reps)
+        cols1 = np.unique(np.linspace(0, n - 1, num=8).astype(int))
+        X1 = np.asfortranarray(Bd[:, cols1.tolist()].cpu().numpy())
+        eta1 = oracle.backward_error(L, X1, np.asfortranarray(B[:, cols1]), 1.0)
         Bd.copy_(Bp)
         hs.trsm(Ld, Bd, 1.0, mixed=True, refine_steps=-1, refine_tol=tol)
         torch.cuda.synchronize()
@@ -430,6 +468,8 @@ def run_mixed(args, torch, hs, cfg):
                      "mixed_ms": round(tmx, 3), "mixed_eta": rmx["backward_error"],
                      "mixed_refine_steps": rmx["refine_steps"], "target_eta": tol,
                      "mixed_solve_only_ms": round(t32, 3),
+                     "mixed_one_step_ms": round(t1s, 3), "mixed_one_step_eta_sampled": eta1,
+                     "speedup_one_step_over_fp64": round(t64 / t1s, 3),
                      "speedup_mixed_over_fp64": round(t64 / tmx, 3),
                      "oracle_eta_sampled": eta_or, "forward_err_vs_oracle": oracle.rel_err_fro(X, ref)})
         log(f"kappa {kappa:.0e}: fp64 {t64:.2f} ms eta {r64['backward_error']:.2e} | mixed {tmx:.2f} ms "
@@ -603,6 +643,19 @@ def run_headline(args, torch, hs, names):
             out[key] = {"error": repr(e)}
         torch.cuda.empty_cache()
         hs.workspace_release()
+    try:
+        out["graph"] = run_graph(sub, torch, hs)
+    except Exception as e:
+        out["graph"] = {"error": repr(e)}
+    try:
+        sub.workload = "mixed"
+        r = run_mixed(sub, torch, hs, dict(W.MIXED), kappas=(1e3, 1e6))
+        out["mixed"] = {"workload": "DTRSM m=8192, n=4096, kappa_inf ~1e3 and ~1e6, seed 3",
+                        "rows": r["mixed"]}
+    except Exception as e:
+        out["mixed"] = {"error": repr(e)}
+    torch.cuda.empty_cache()
+    hs.workspace_release()
     try:
         sub.workload = "serving"
         r = run_serving(sub, torch, hs)
