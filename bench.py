@@ -329,9 +329,9 @@ def run_batched(args, torch, hs, cfg):
             "step_ms_events": ev_ms,
             "step_rate_gbs": round(byts / (ev_ms * 1e-3) / 1e9, 2),
             "per_unit": "per problem: 16 (m(m+1)/2 + 2mn) bytes (lower triangle of L once, B read and "
-                        "written once); a launch serves one (dtype, diag, ceil(m/8)) group, so bytes per "
-                        "launch = bytes per step / group launches per step; launches of one step run "
-                        "concurrently on separate streams"}
+                        "written once); a launch serves one (dtype, diag) group, so bytes per "
+                        "launch = bytes per step / group launches per step (one here: every problem is "
+                        "complex with a non-unit diagonal)"}
 
     # One-shot API (host descriptors uploaded each call) for reference.
     oneshot_ms = time_gpu(lambda: hs.trsm_batched(probs), max(2, args.steps), 1, torch)

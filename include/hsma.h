@@ -207,8 +207,8 @@ typedef struct {
  * diagonal kinds and alphas may all differ.  Each problem is validated with
  * the hsma_trsm rules first; on the first invalid one its index goes to
  * *first_bad (if non-NULL), its status is returned and nothing is enqueued.
- * Problems with m <= 64 run in a handful of persistent grouped launches
- * (one per data type, diagonal kind and ceil(m/8)); the rest take the
+ * Problems with m <= 64 run in persistent grouped launches (one per data
+ * type and diagonal kind, longest problems first); the rest take the
  * blocked path grouped: every problem keeps the schedule (I_B, inversions,
  * recursion) it gets alone, so its result is bit-for-bit the same, but the
  * k-th operation of all of them shares one launch.  Both parts are forked

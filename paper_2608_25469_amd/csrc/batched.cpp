@@ -3,9 +3,8 @@
 //
 // Problems with m <= 64 become work items -- one per 64-column panel -- of
 // the persistent small-solve kernel.  Items are grouped by (data type,
-// diagonal kind, ceil(m/8)) because each group runs a kernel instance
-// specialised for its row bound; inside a group items are ordered by
-// decreasing cost (longest processing time first).  The item table, with one
+// diagonal kind); inside a group items are ordered by decreasing cost
+// (longest processing time first).  The item table, with one
 // zeroed work counter per group in front, is uploaded in one copy; the group
 // launches are forked onto library-owned streams so they overlap on the
 // device, and joined back into the caller's stream.  Problems with m > 64
@@ -51,12 +50,18 @@ struct Item {
     double ar, ai;
 };
 
-constexpr int kGroups = 2 * 2 * 8;  // complex x unit x chunk count
+constexpr int kGroups = 2 * 2 * 8;  // complex x unit x kernel instance (one used per pair)
 constexpr int kForkStreams = 8;
 constexpr size_t kHeader = 256;     // kGroups int32 counters, padded
 
+// Every small item of a (data type, diagonal kind) runs in one persistent
+// launch of the 64-row instance: its left-looking walk skips the 16-row
+// blocks past each item's m, so the work still follows m, and one launch
+// keeps the whole GPU on one longest-first queue instead of several
+// launches competing for it.
 int group_of(bool cx, bool unit, int m) {
-    return ((cx ? 1 : 0) * 2 + (unit ? 1 : 0)) * 8 + ((m + 7) / 8 - 1);
+    (void)m;
+    return ((cx ? 1 : 0) * 2 + (unit ? 1 : 0)) * 8 + 7;
 }
 
 struct DevicePool {

@@ -541,7 +541,7 @@ struct SmallItem {
 };
 
 // Device-side descriptor table of a grouped launch: items of one
-// (dtype, unit, chunk-count) group and the counter the persistent
+// (dtype, unit) group and the counter the persistent
 // workgroups draw from.  The counter is zero when the table is uploaded.
 struct SmallGroup {
     const SmallItem *items;
