@@ -38,7 +38,6 @@
 namespace hsma {
 namespace smallk {
 
-typedef __attribute__((address_space(4))) const double sdouble;  // scalar-cache loads
 
 __device__ __forceinline__ double readlane_d(double v, int lane) {
     const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);

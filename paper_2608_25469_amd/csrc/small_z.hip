@@ -113,7 +113,7 @@ hsma_status launch_small_group_z(bool unit, int nch, const void *grp_items, int 
     return HSMA_SUCCESS;
 }
 
-// Resident wavefronts per CU of the grouped kernel for one chunk count.
+// Resident wavefronts per CU of the grouped kernel instance for row bound 8 * nch.
 int small_group_occupancy_z(bool unit, int nch) {
     const void *k = unit ? small_kernel_ptr<true>(nch) : small_kernel_ptr<false>(nch);
     int blocks = 0;
