@@ -45,6 +45,13 @@ struct __attribute__((aligned(8))) d2 {
     double x, y;
 };
 
+// 16-byte load of two doubles through a generic or a global pointer.
+__device__ __forceinline__ d2 ld_pair(const double *p) { return *reinterpret_cast<const d2 *>(p); }
+__device__ __forceinline__ d2 ld_pair(const HSMA_GLOBAL double *p) {
+    const dbl2u t = *reinterpret_cast<const HSMA_GLOBAL dbl2u *>(p);
+    return d2{t.x, t.y};
+}
+
 constexpr int BK = 16;
 
 // Workgroups per CU that the tile's LDS ring allows (160 KB per CU, at most
@@ -65,10 +72,12 @@ __host__ __device__ constexpr int occ_for(int bm, int bn) {
 
 // One BM x BN tile (tm, tn) of C = beta C + alpha A B; Ag, Bg, Cg are the
 // operand bases of this product (after any batch offset).
-template <bool CX, int BM, int BN, int WM, int WN>
-__device__ __forceinline__ void gemm_tile(const GemmParams &p, const double *__restrict__ Ag,
-                                          const double *__restrict__ Bg, double *__restrict__ Cg,
-                                          int tm, int tn) {
+// GD is double (pointers the compiler already knows to be global: kernel
+// arguments) or HSMA_GLOBAL double (pointers read from a descriptor table).
+template <bool CX, int BM, int BN, int WM, int WN, typename GD>
+__device__ __forceinline__ void gemm_tile(const GemmParams &p, const GD *__restrict__ Ag,
+                                          const GD *__restrict__ Bg, GD *__restrict__ Cg, int tm,
+                                          int tn) {
     constexpr int TM = BM / WM, TN = BN / WN;
     constexpr int FM = TM / 16, FN = TN / 16;
     constexpr int LDA_S = BM + 4;    // LDS stride of the A tile (per k)
@@ -106,9 +115,9 @@ __device__ __forceinline__ void gemm_tile(const GemmParams &p, const double *__r
                 (void)gk;
                 d2 v = {0.0, 0.0};
                 if (gc < K) {
-                    const double *src = Ag + (int64_t)gc * p.lda + gr;
+                    const GD *src = Ag + (int64_t)gc * p.lda + gr;
                     if (gr + 1 < M) {
-                        v = *reinterpret_cast<const d2 *>(src);
+                        v = ld_pair(src);
                     } else if (gr < M) {
                         v.x = src[0];
                     }
@@ -128,7 +137,7 @@ __device__ __forceinline__ void gemm_tile(const GemmParams &p, const double *__r
                 const int gr = m0 / 2 + ic, gc = k0 / 2 + kc;
                 d2 v = {0.0, 0.0};
                 if (gc < K / 2 && gr < M / 2) {
-                    v = *reinterpret_cast<const d2 *>(Ag + 2 * ((int64_t)gc * p.lda + gr));
+                    v = ld_pair(Ag + 2 * ((int64_t)gc * p.lda + gr));
                     if (p.tri_a) {
                         if (gr < gc) v.x = v.y = 0.0;
                         if (p.tri_a == 2 && gr == gc) {
@@ -171,9 +180,9 @@ __device__ __forceinline__ void gemm_tile(const GemmParams &p, const double *__r
             const int gn = n0 + jj, gk = k0 + kk;
             d2 v = {0.0, 0.0};
             if (gn < N) {
-                const double *src = Bg + (int64_t)gn * p.ldb + gk;
+                const GD *src = Bg + (int64_t)gn * p.ldb + gk;
                 if (gk + 1 < K) {
-                    v = *reinterpret_cast<const d2 *>(src);
+                    v = ld_pair(src);
                 } else if (gk < K) {
                     v.x = src[0];
                 }
@@ -247,7 +256,7 @@ __device__ __forceinline__ void gemm_tile(const GemmParams &p, const double *__r
             const int col = n0 + wn0 + 16 * j + lr;
             const int row = m0 + wm0 + 16 * i + 4 * lk;
             if (col >= N) continue;
-            double *dst = Cg + (int64_t)col * p.ldc + row;
+            GD *dst = Cg + (int64_t)col * p.ldc + row;
             double v[4] = {acc[i][j][0], acc[i][j][1], acc[i][j][2], acc[i][j][3]};
             if (CX) {
 #pragma unroll
@@ -320,7 +329,8 @@ __global__ __launch_bounds__(256, (occ_for(BM, BN))) void hsma_gemm_grouped(
     const GemmParams p = descs[lo];
     const int local = t - p.tile0;
     if (local < 0 || local >= p.tiles_m * p.tiles_n) return;
-    gemm_tile<CX, BM, BN, WM, WN>(p, p.A, p.B, p.C, local % p.tiles_m, local / p.tiles_m);
+    gemm_tile<CX, BM, BN, WM, WN>(p, (const HSMA_GLOBAL double *)p.A, (const HSMA_GLOBAL double *)p.B,
+                                  (HSMA_GLOBAL double *)p.C, local % p.tiles_m, local / p.tiles_m);
 }
 
 template <bool CX, int BM, int BN, int WM, int WN, int ROLE>

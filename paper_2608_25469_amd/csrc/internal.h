@@ -25,6 +25,17 @@ hsma_status hip_fail(hipError_t e);
         if (s_ != HSMA_SUCCESS) return s_;               \
     } while (0)
 
+// Global-memory address space.  Pointers that kernels read out of descriptor
+// tables are generic; loads and stores through a generic pointer become FLAT
+// instructions, which count against the LDS wait counter as well, so every
+// wait for an LDS read would also wait for the global loads in flight.
+// Kernels convert such pointers with a cast to HSMA_GLOBAL before use.
+#define HSMA_GLOBAL __attribute__((address_space(1)))
+
+// Two doubles moved as one 16-byte access (a complex value, or two
+// consecutive real entries); it assumes only 8-byte alignment.
+typedef double dbl2u __attribute__((ext_vector_type(2), aligned(8)));
+
 // Complex scalar as two doubles (interleaved storage).
 struct cplx {
     double re, im;

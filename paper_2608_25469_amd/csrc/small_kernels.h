@@ -11,9 +11,12 @@
 // column k+1 is read from LDS into ceil(m/16) VGPRs laid out so that each
 // 16-lane row of the wavefront holds 16 consecutive rows of the column, and
 // each coefficient reaches all lanes through the 64-bit DPP row_newbcast
-// broadcast, which feeds v_fma_f64 with no further memory traffic.  The
-// column for the next step is read before the current step's arithmetic, so
-// LDS latency hides behind the dependency chain.
+// broadcast with no further memory traffic.  In the left-looking walk the
+// broadcast is the DPP source operand of the multiply-add itself
+// (v_fmac_f64_dpp, dpp_fma.h), so a real update costs one VALU instruction
+// and a complex one four.  The column for the next step is read before the
+// current step's arithmetic, so LDS latency hides behind the dependency
+// chain.
 //
 // The loop nest is fully unrolled for a compile-time row bound MAXM (a
 // multiple of 8) and guarded by the runtime m.  Two walks share this
@@ -34,6 +37,7 @@
 #include <type_traits>
 
 #include "internal.h"
+#include "dpp_fma.h"
 
 namespace hsma {
 namespace smallk {
@@ -192,17 +196,17 @@ struct Panel {
         int lane = threadIdx.x & 63;
         asm volatile("" : "+v"(lane));
         const bool active = lane < ncols;
-        double *__restrict__ bc = B + ES * (int64_t)(active ? lane : 0) * ldb;
+        HSMA_GLOBAL double *__restrict__ bc = (HSMA_GLOBAL double *)(B + ES * (int64_t)(active ? lane : 0) * ldb);
 
         // Reciprocal of the diagonal, one entry per lane: 1/d or conj(d)/|d|^2.
         double rr = 1.0, ri = 0.0;
         if (!UNIT && lane < m) {
-            const double *d = A + ES * ((int64_t)lane + (int64_t)lane * lda);
+            const HSMA_GLOBAL double *d = (const HSMA_GLOBAL double *)(A + ES * ((int64_t)lane + (int64_t)lane * lda));
             if (CX) {
-                const dpair v = *reinterpret_cast<const dpair *>(d);
-                const double den = v.x * v.x + v.y * v.y;
-                rr = v.x / den;
-                ri = -v.y / den;
+                const double vx = d[0], vy = d[1];
+                const double den = vx * vx + vy * vy;
+                rr = vx / den;
+                ri = -vy / den;
             } else {
                 rr = 1.0 / d[0];
             }
@@ -217,7 +221,7 @@ struct Panel {
                 yr[i] = (i == lane) ? 1.0 : 0.0;
                 yi[i] = 0.0;
             } else if (CX) {
-                const dpair v = reinterpret_cast<const dpair *>(bc)[ic];
+                const dbl2u v = reinterpret_cast<const HSMA_GLOBAL dbl2u *>(bc)[ic];
                 yr[i] = v.x;
                 yi[i] = v.y;
             } else {
@@ -284,7 +288,7 @@ struct Panel {
             for (int i = 0; i < MAXM; ++i) {
                 if (i < m) {
                     if (CX)
-                        reinterpret_cast<dpair *>(bc)[i] = dpair{yr[i], yi[i]};
+                        reinterpret_cast<HSMA_GLOBAL dbl2u *>(bc)[i] = dbl2u{yr[i], yi[i]};
                     else
                         bc[i] = yr[i];
                 }
@@ -402,12 +406,16 @@ struct PanelLL {
                     }
                 }
                 const double xr = yr[KK], xi = yi[KK];
-                static_for<KK + 1, BR>([&](auto I) {
-                    constexpr int i = decltype(I)::value;
-                    const double lr = bcast16<i & 15>(cr);
-                    const double li = CX ? bcast16<i & 15>(ci) : 0.0;
-                    fms<CX>(yr[i], yi[i], lr, li, xr, xi);
-                });
+                if constexpr (BR == RB) {
+                    if constexpr (KK + 1 < RB) fnma_rows<CX, KK + 1>(yr, yi, cr, ci, xr, xi);
+                } else {
+                    static_for<KK + 1, BR>([&](auto I) {
+                        constexpr int i = decltype(I)::value;
+                        const double lr = bcast16<i & 15>(cr);
+                        const double li = CX ? bcast16<i & 15>(ci) : 0.0;
+                        fms<CX>(yr[i], yi[i], lr, li, xr, xi);
+                    });
+                }
                 diag_step<R, BR, KK + 1>(Lp, m, lane, rr, ri, yr, yi, nr, ni);
             }
         }
@@ -417,7 +425,7 @@ struct PanelLL {
     // diagonal triangle, store.
     template <int R>
     static __device__ __forceinline__ void block(const double *__restrict__ A, int64_t lda,
-                                                 double *Lp, double *__restrict__ bc, bool active,
+                                                 double *Lp, HSMA_GLOBAL double *__restrict__ bc, bool active,
                                                  int m, int lane, double rr, double ri, cplx alpha) {
         if constexpr (R < NB) {
             constexpr int BR = (MAXM - R * RB) < RB ? (MAXM - R * RB) : RB;  // rows of this block
@@ -430,7 +438,7 @@ struct PanelLL {
                     const int g = R * RB + i;
                     const int gc = g < m ? g : m - 1;
                     if (CX) {
-                        const dpair v = reinterpret_cast<const dpair *>(bc)[gc];
+                        const dbl2u v = reinterpret_cast<const HSMA_GLOBAL dbl2u *>(bc)[gc];
                         yr[i] = v.x;
                         yi[i] = v.y;
                     } else {
@@ -460,7 +468,7 @@ struct PanelLL {
 #pragma unroll
                     for (int k = 0; k < RB; ++k) {
                         if (CX) {
-                            const dpair v = reinterpret_cast<const dpair *>(bc)[Kb * RB + k];
+                            const dbl2u v = reinterpret_cast<const HSMA_GLOBAL dbl2u *>(bc)[Kb * RB + k];
                             xr[k] = v.x;
                             xi[k] = v.y;
                         } else {
@@ -474,12 +482,16 @@ struct PanelLL {
                         constexpr int kk = decltype(KK)::value;
                         double nr = 0.0, ni = 0.0;
                         if constexpr (kk + 1 < RB) coef(Lp, lane, Kb * RB + kk + 1, nr, ni);
-                        static_for<0, BR>([&](auto I) {
-                            constexpr int i = decltype(I)::value;
-                            const double lr = bcast16<i & 15>(cr);
-                            const double li = CX ? bcast16<i & 15>(ci) : 0.0;
-                            fms<CX>(yr[i], yi[i], lr, li, xr[kk], xi[kk]);
-                        });
+                        if constexpr (BR == RB) {
+                            fnma_rows<CX, 0>(yr, yi, cr, ci, xr[kk], xi[kk]);
+                        } else {
+                            static_for<0, BR>([&](auto I) {
+                                constexpr int i = decltype(I)::value;
+                                const double lr = bcast16<i & 15>(cr);
+                                const double li = CX ? bcast16<i & 15>(ci) : 0.0;
+                                fms<CX>(yr[i], yi[i], lr, li, xr[kk], xi[kk]);
+                            });
+                        }
                         cr = nr;
                         ci = ni;
                     });
@@ -492,7 +504,7 @@ struct PanelLL {
                     for (int i = 0; i < BR; ++i) {
                         if (R * RB + i < m) {
                             if (CX)
-                                reinterpret_cast<dpair *>(bc)[R * RB + i] = dpair{yr[i], yi[i]};
+                                reinterpret_cast<HSMA_GLOBAL dbl2u *>(bc)[R * RB + i] = dbl2u{yr[i], yi[i]};
                             else
                                 bc[R * RB + i] = yr[i];
                         }
@@ -510,16 +522,16 @@ struct PanelLL {
         int lane = threadIdx.x & 63;
         asm volatile("" : "+v"(lane));
         const bool active = lane < ncols;
-        double *__restrict__ bc = B + ES * (int64_t)(active ? lane : 0) * ldb;
+        HSMA_GLOBAL double *__restrict__ bc = (HSMA_GLOBAL double *)(B + ES * (int64_t)(active ? lane : 0) * ldb);
 
         double rr = 1.0, ri = 0.0;
         if (!UNIT && lane < m) {
-            const double *d = A + ES * ((int64_t)lane + (int64_t)lane * lda);
+            const HSMA_GLOBAL double *d = (const HSMA_GLOBAL double *)(A + ES * ((int64_t)lane + (int64_t)lane * lda));
             if (CX) {
-                const dpair v = *reinterpret_cast<const dpair *>(d);
-                const double den = v.x * v.x + v.y * v.y;
-                rr = v.x / den;
-                ri = -v.y / den;
+                const double vx = d[0], vy = d[1];
+                const double den = vx * vx + vy * vy;
+                rr = vx / den;
+                ri = -vy / den;
             } else {
                 rr = 1.0 / d[0];
             }
@@ -582,7 +594,7 @@ void hsma_small_solve(SmallItem one, SmallGroup grp) {
         if (d.ar == 0.0 && d.ai == 0.0) {
             // alpha = 0: B := 0, neither A nor B is read.
             if (lane < d.ncols) {
-                double *bc = d.B + (CX ? 2 : 1) * (int64_t)lane * d.ldb;
+                HSMA_GLOBAL double *bc = (HSMA_GLOBAL double *)(d.B + (CX ? 2 : 1) * (int64_t)lane * d.ldb);
                 for (int i = 0; i < (CX ? 2 : 1) * d.m; ++i) bc[i] = 0.0;
             }
             continue;
