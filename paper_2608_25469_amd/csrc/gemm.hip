@@ -63,6 +63,10 @@ __host__ __device__ constexpr int occ_for(int bm, int bn) {
     return (160 * 1024 / lds_bytes(bm, bn)) >= 3 ? 3 : ((160 * 1024 / lds_bytes(bm, bn)) >= 2 ? 2 : 1);
 }
 
+#ifndef HSMA_UPD_MIN_WG_PER_CU
+#define HSMA_UPD_MIN_WG_PER_CU 4
+#endif
+
 #ifndef HSMA_UPD_BM
 #define HSMA_UPD_BM 128
 #define HSMA_UPD_BN 128
@@ -363,8 +367,19 @@ hsma_status launch_role(GemmParams p, int count, hipStream_t s) {
         return HSMA_NOT_SUPPORTED;
     }
     if (p.M <= 64 && p.N <= 64) return launch_t<CX, 64, 64, 2, 2, ROLE>(p, count, s);
-    if (ROLE == (int)GemmRole::Update)
-        return launch_t<CX, HSMA_UPD_BM, HSMA_UPD_BN, HSMA_UPD_WM, HSMA_UPD_WN, ROLE>(p, count, s);
+    if (ROLE == (int)GemmRole::Update) {
+        // The trailing updates of the deepest recursion levels are thin
+        // (M = K = one or two block sizes): below HSMA_UPD_MIN_WG_PER_CU
+        // workgroups per CU, narrower tiles keep every CU busy.
+        DeviceInfo dev;
+        const int64_t cus = (device_info(&dev) == HSMA_SUCCESS && dev.num_cus > 0) ? dev.num_cus : 256;
+        const int64_t want = HSMA_UPD_MIN_WG_PER_CU * cus;
+        const int64_t rows128 = (p.M + 127) / 128;
+        if (rows128 * ((p.N + HSMA_UPD_BN - 1) / HSMA_UPD_BN) * count >= want)
+            return launch_t<CX, HSMA_UPD_BM, HSMA_UPD_BN, HSMA_UPD_WM, HSMA_UPD_WN, ROLE>(p, count, s);
+        if (rows128 * ((p.N + 63) / 64) * count >= want) return launch_t<CX, 128, 64, 2, 2, ROLE>(p, count, s);
+        return launch_t<CX, 64, 64, 2, 2, ROLE>(p, count, s);
+    }
     return launch_t<CX, 128, 128, 2, 2, ROLE>(p, count, s);
 }
 
