@@ -380,6 +380,52 @@ struct PanelLL {
         }
     }
 
+    // A finished block goes back to B through LDS so that each store
+    // instruction writes four whole 16-row column segments (four 256-byte
+    // runs for complex, 128-byte runs for real) instead of one element of 64
+    // different columns.  Chunk c of LDS holds columns 4c..4c+3, the element
+    // (column 4c + r, row i) in slot 16 (r ^ f) + (i + r + 4 (c % 4)) % 16
+    // with f = (c / 4) % 2: the lanes of a quarter (complex) or half (real)
+    // wavefront then hit distinct LDS banks when they write their rows, and
+    // every read of a chunk is contiguous.
+    static constexpr bool COALESCED_STORE = (MAXM == 64);
+
+    template <int R>
+    static __device__ __forceinline__ void store_block(double *Lp, HSMA_GLOBAL double *__restrict__ Bp,
+                                                       int64_t ldb, int ncols, int m, int lane,
+                                                       const double (&yr)[RB], const double (&yi)[RB]) {
+        __syncthreads();  // the panel's reads are complete
+        {
+            const int c = lane >> 2, r = lane & 3, q = c & 3, f = (c >> 2) & 1;
+#pragma unroll
+            for (int i = 0; i < RB; ++i) {
+                double *p = Lp + ES * (c * 64 + 16 * (r ^ f) + ((i + r + 4 * q) & 15));
+                if (CX) {
+                    p[0] = yr[i];
+                    p[1] = yi[i];
+                } else {
+                    p[0] = yr[i];
+                }
+            }
+        }
+        __syncthreads();  // the block is in LDS
+#pragma unroll
+        for (int c = 0; c < 16; ++c) {
+            const int f = (c >> 2) & 1, q = c & 3;
+            const int r = (lane >> 4) ^ f;
+            const int i = ((lane & 15) - r - 4 * q) & 15;
+            const int col = 4 * c + r;
+            const double *p = Lp + ES * (c * 64 + lane);
+            if (col < ncols && R * RB + i < m) {
+                HSMA_GLOBAL double *dst = Bp + ES * ((int64_t)col * ldb + R * RB + i);
+                if (CX)
+                    *reinterpret_cast<HSMA_GLOBAL dbl2u *>(dst) = dbl2u{p[0], p[1]};
+                else
+                    dst[0] = p[0];
+            }
+        }
+    }
+
     // Diagonal step KK of block R: x = y[KK] / l_KK, then rows KK+1.. of the
     // block receive -l_iK x.  c holds column K's coefficients (read one step
     // earlier); the next column's are read first.  Steps nest so that the
@@ -426,6 +472,7 @@ struct PanelLL {
     template <int R>
     static __device__ __forceinline__ void block(const double *__restrict__ A, int64_t lda,
                                                  double *Lp, HSMA_GLOBAL double *__restrict__ bc, bool active,
+                                                 HSMA_GLOBAL double *__restrict__ Bp, int64_t ldb, int ncols,
                                                  int m, int lane, double rr, double ri, cplx alpha) {
         if constexpr (R < NB) {
             constexpr int BR = (MAXM - R * RB) < RB ? (MAXM - R * RB) : RB;  // rows of this block
@@ -499,7 +546,9 @@ struct PanelLL {
                 double cr, ci;
                 coef(Lp, lane, R * RB, cr, ci);
                 diag_step<R, BR, 0>(Lp, m, lane, rr, ri, yr, yi, cr, ci);
-                if (active) {
+                if constexpr (COALESCED_STORE && BR == RB) {
+                    store_block<R>(Lp, Bp, ldb, ncols, m, lane, yr, yi);
+                } else if (active) {
 #pragma unroll
                     for (int i = 0; i < BR; ++i) {
                         if (R * RB + i < m) {
@@ -510,7 +559,7 @@ struct PanelLL {
                         }
                     }
                 }
-                block<R + 1>(A, lda, Lp, bc, active, m, lane, rr, ri, alpha);
+                block<R + 1>(A, lda, Lp, bc, active, Bp, ldb, ncols, m, lane, rr, ri, alpha);
             }
         }
     }
@@ -536,8 +585,8 @@ struct PanelLL {
                 rr = 1.0 / d[0];
             }
         }
-        __shared__ double Lp[ES * PANEL];
-        block<0>(A, lda, Lp, bc, active, m, lane, rr, ri, alpha);
+        __shared__ double Lp[ES * (COALESCED_STORE && PANEL < RB * 64 ? RB * 64 : PANEL)];
+        block<0>(A, lda, Lp, bc, active, (HSMA_GLOBAL double *)B, ldb, ncols, m, lane, rr, ri, alpha);
         __syncthreads();  // LDS is reused by the next item of a persistent wave
     }
 };
