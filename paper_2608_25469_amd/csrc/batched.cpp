@@ -4,8 +4,8 @@
 // Problems with m <= 64 become work items -- one per 64-column panel -- of
 // the persistent small-solve kernel.  Items are grouped by (data type,
 // diagonal kind); inside a group items are ordered by decreasing cost
-// (longest processing time first).  The item table, with one
-// zeroed work counter per group in front, is uploaded in one copy; the group
+// (longest processing time first).  The item table, with a zeroed work
+// counter and exit counter per group in front, is uploaded in one copy; the group
 // launches are forked onto library-owned streams so they overlap on the
 // device, and joined back into the caller's stream.  Problems with m > 64
 // take the grouped blocked path (grouped.cpp) on one more forked stream.
@@ -32,9 +32,9 @@ hsma_status grouped_blocked(const hsma_problem *probs, int64_t count, hipStream_
 
 // From small_d.hip / small_z.hip
 hsma_status launch_small_group_d(bool unit, int nch, const void *items, int count,
-                                 int32_t *counter, int wgs, hipStream_t s);
+                                 int32_t *counter, int32_t *done, int wgs, hipStream_t s);
 hsma_status launch_small_group_z(bool unit, int nch, const void *items, int count,
-                                 int32_t *counter, int wgs, hipStream_t s);
+                                 int32_t *counter, int32_t *done, int wgs, hipStream_t s);
 int small_group_occupancy_d(bool unit, int nch);
 int small_group_occupancy_z(bool unit, int nch);
 size_t small_item_bytes_d();
@@ -52,7 +52,8 @@ struct Item {
 
 constexpr int kGroups = 2 * 2 * 8;  // complex x unit x kernel instance (one used per pair)
 constexpr int kForkStreams = 8;
-constexpr size_t kHeader = 256;     // kGroups int32 counters, padded
+constexpr size_t kHeader = 256;     // kGroups int32 work counters, then kGroups exit counters
+static_assert(2 * kGroups * sizeof(int32_t) <= kHeader, "counters fit the header");
 
 // Every small item of a (data type, diagonal kind) runs in one persistent
 // launch of the 64-row instance: its left-looking walk skips the 16-row
@@ -206,16 +207,20 @@ static hsma_status run_table(const BatchTable &t, hipStream_t s, bool fork = tru
     for (int g = 0; g < kGroups; ++g) ngroups += t.count[g] > 0;
     if (!t.large.empty()) ngroups += 1;
     if (ngroups > 0) {
-        hipEvent_t fork_ev;
-        HSMA_HIP(hipEventCreateWithFlags(&fork_ev, hipEventDisableTiming));
-        HSMA_HIP(hipEventRecord(fork_ev, s));
+        // One launch (or no fork) stays on s: no events.
+        const bool forking = fork && ngroups > 1;
+        hipEvent_t fork_ev = nullptr;
+        if (forking) {
+            HSMA_HIP(hipEventCreateWithFlags(&fork_ev, hipEventDisableTiming));
+            HSMA_HIP(hipEventRecord(fork_ev, s));
+        }
         std::vector<hipEvent_t> joins;
         int k = 0;
         hsma_status st = HSMA_SUCCESS;
         // Largest-row groups first: they hold the longest items.
         for (int g = kGroups - 1; g >= 0 && st == HSMA_SUCCESS; --g) {
             if (t.count[g] == 0) continue;
-            hipStream_t fs = (ngroups == 1 || !fork) ? s : pool->fork[k++ % kForkStreams];
+            hipStream_t fs = forking ? pool->fork[k++ % kForkStreams] : s;
             if (fs != s) HSMA_HIP(hipStreamWaitEvent(fs, fork_ev, 0));
             const bool cx = g >= 16, unit = (g / 8) % 2;
             const int nch = g % 8 + 1;
@@ -225,8 +230,8 @@ static hsma_status run_table(const BatchTable &t, hipStream_t s, bool fork = tru
             int32_t *counter = reinterpret_cast<int32_t *>(const_cast<unsigned char *>(base)) + g;
             {
                 ProfScope prof(HSMA_PHASE_SMALL, 0.0, fs);
-                st = cx ? launch_small_group_z(unit, nch, items, t.count[g], counter, wgs, fs)
-                        : launch_small_group_d(unit, nch, items, t.count[g], counter, wgs, fs);
+                st = cx ? launch_small_group_z(unit, nch, items, t.count[g], counter, counter + kGroups, wgs, fs)
+                        : launch_small_group_d(unit, nch, items, t.count[g], counter, counter + kGroups, wgs, fs);
             }
             if (fs != s) {
                 hipEvent_t j;
@@ -237,7 +242,7 @@ static hsma_status run_table(const BatchTable &t, hipStream_t s, bool fork = tru
         }
         // The large problems run beside the small groups.
         if (st == HSMA_SUCCESS && !t.large.empty()) {
-            hipStream_t fs = (ngroups == 1 || !fork) ? s : pool->fork[k++ % kForkStreams];
+            hipStream_t fs = forking ? pool->fork[k++ % kForkStreams] : s;
             if (fs != s) HSMA_HIP(hipStreamWaitEvent(fs, fork_ev, 0));
             st = run_large(t.large, fs);
             if (fs != s) {
@@ -251,7 +256,7 @@ static hsma_status run_table(const BatchTable &t, hipStream_t s, bool fork = tru
             HSMA_HIP(hipStreamWaitEvent(s, j, 0));
             HSMA_HIP(hipEventDestroy(j));
         }
-        HSMA_HIP(hipEventDestroy(fork_ev));
+        if (fork_ev) HSMA_HIP(hipEventDestroy(fork_ev));
         HSMA_TRY(st);
     }
     return HSMA_SUCCESS;
@@ -394,11 +399,8 @@ hsma_status hsma_batch_plan_execute(hsma_batch_plan *plan, hsma_stream_t stream)
     HSMA_HIP(hipGetDevice(&dev));
     if (dev != plan->device) return HSMA_INVALID_VALUE;
     hipStream_t s = static_cast<hipStream_t>(stream);
-    if (plan->table.dev) {
-        // Counters back to zero (a kernel, so the sequence can be captured).
-        HSMA_TRY(launch_zero(kHeader / sizeof(double), 1, 1, static_cast<double *>(plan->table.dev),
-                             kHeader / sizeof(double), s));
-    }
+    // The counters are zero: the upload wrote them so, and every completed
+    // group launch returns its own to zero.
     return run_table(plan->table, s);
 }
 

@@ -607,6 +607,7 @@ struct SmallGroup {
     const SmallItem *items;
     int32_t count;
     int32_t *counter;
+    int32_t *done;    // wavefronts that have left; zero when the table is uploaded
 };
 
 // Single problem (items == nullptr): workgroup b solves panel b of `one`.
@@ -637,7 +638,16 @@ void hsma_small_solve(SmallItem one, SmallGroup grp) {
             int idx = 0;
             if (lane == 0) idx = atomicAdd(grp.counter, 1);
             idx = __builtin_amdgcn_readlane(idx, 0);
-            if (idx >= grp.count) break;
+            if (idx >= grp.count) {
+                // The last wavefront to leave returns both counters to zero,
+                // so the table can run again without a reset.  Every other
+                // wavefront's final claim has returned before its exit count.
+                if (lane == 0 && atomicAdd(grp.done, 1) == (int)gridDim.x - 1) {
+                    atomicExch(grp.counter, 0);
+                    atomicExch(grp.done, 0);
+                }
+                break;
+            }
             d = grp.items[idx];
         }
         if (d.ar == 0.0 && d.ai == 0.0) {

@@ -92,7 +92,7 @@ hsma_status launch_small_z(bool unit, int m, int64_t n, cplx alpha, const double
     const int64_t panels = (n + 63) / 64;
     if (panels > 0x7fffffff || n > 0x7fffffff) return HSMA_INVALID_SIZE;
     SmallItem one{A, B, lda, ldb, m, (int32_t)n, alpha.re, alpha.im};
-    SmallGroup none{nullptr, 0, nullptr};
+    SmallGroup none{nullptr, 0, nullptr, nullptr};
     const int nch = (m + 7) / 8;
     if (nch < 1 || nch > 8) return HSMA_INVALID_SIZE;
     if (unit) small_launch<true>(nch, dim3((unsigned)panels), one, none, s);
@@ -101,11 +101,12 @@ hsma_status launch_small_z(bool unit, int m, int64_t n, cplx alpha, const double
     return HSMA_SUCCESS;
 }
 
-// Persistent grouped launch over `grp` (device table) with `wgs` workgroups.
+// Persistent grouped launch over `grp` (device table) with `wgs` workgroups;
+// counter and done start at zero and are zero again when the launch ends.
 hsma_status launch_small_group_z(bool unit, int nch, const void *grp_items, int count,
-                                    int32_t *counter, int wgs, hipStream_t s) {
+                                    int32_t *counter, int32_t *done, int wgs, hipStream_t s) {
     SmallItem one{};
-    SmallGroup grp{static_cast<const SmallItem *>(grp_items), count, counter};
+    SmallGroup grp{static_cast<const SmallItem *>(grp_items), count, counter, done};
     if (nch < 1 || nch > 8 || wgs < 1) return HSMA_INVALID_SIZE;
     if (unit) small_launch<true>(nch, dim3(wgs), one, grp, s);
     else small_launch<false>(nch, dim3(wgs), one, grp, s);
