@@ -29,8 +29,11 @@
 // traffic overlaps the chain (the load/compute/store overlap of Sec. 4.2.1,
 // Alg. 1, obtained by full unrolling and the hardware's in-order waits).
 //
-// Reciprocals of the diagonal are computed once per wavefront, one per lane,
-// and broadcast to the whole wave with v_readlane when row k is divided.
+// Reciprocals of the diagonal are computed one per lane and broadcast to the
+// whole wave with v_readlane when row k is divided: once per wavefront in the
+// right-looking walk, per 16-row block from the staged panel in the
+// left-looking one (so no separate load of the diagonal precedes the first
+// block).
 
 #pragma once
 
@@ -440,9 +443,9 @@ struct PanelLL {
                 double nr = 0.0, ni = 0.0;
                 if constexpr (KK + 1 < BR) coef(Lp, lane, K + 1, nr, ni);
                 if (!UNIT) {
-                    const double dr = readlane_d(rr, K);
+                    const double dr = readlane_d(rr, KK);
                     if (CX) {
-                        const double di = readlane_d(ri, K);
+                        const double di = readlane_d(ri, KK);
                         const double tr = yr[KK] * dr - yi[KK] * di;
                         const double ti = yr[KK] * di + yi[KK] * dr;
                         yr[KK] = tr;
@@ -473,7 +476,7 @@ struct PanelLL {
     static __device__ __forceinline__ void block(const double *__restrict__ A, int64_t lda,
                                                  double *Lp, HSMA_GLOBAL double *__restrict__ bc, bool active,
                                                  HSMA_GLOBAL double *__restrict__ Bp, int64_t ldb, int ncols,
-                                                 int m, int lane, double rr, double ri, cplx alpha) {
+                                                 int m, int lane, cplx alpha) {
         if constexpr (R < NB) {
             constexpr int BR = (MAXM - R * RB) < RB ? (MAXM - R * RB) : RB;  // rows of this block
             if (R * RB < m) {
@@ -543,6 +546,20 @@ struct PanelLL {
                         ci = ni;
                     });
                 });
+                // Reciprocals of this block's diagonal, from the staged panel:
+                // lane l holds row R*16 + l%16 (1/d, or conj(d)/|d|^2).
+                double rr = 1.0, ri = 0.0;
+                if (!UNIT && (lane & 15) < BR) {
+                    double vx, vy;
+                    coef(Lp, lane, R * RB + (lane & 15), vx, vy);
+                    if (CX) {
+                        const double den = vx * vx + vy * vy;
+                        rr = vx / den;
+                        ri = -vy / den;
+                    } else {
+                        rr = 1.0 / vx;
+                    }
+                }
                 double cr, ci;
                 coef(Lp, lane, R * RB, cr, ci);
                 diag_step<R, BR, 0>(Lp, m, lane, rr, ri, yr, yi, cr, ci);
@@ -559,7 +576,7 @@ struct PanelLL {
                         }
                     }
                 }
-                block<R + 1>(A, lda, Lp, bc, active, Bp, ldb, ncols, m, lane, rr, ri, alpha);
+                block<R + 1>(A, lda, Lp, bc, active, Bp, ldb, ncols, m, lane, alpha);
             }
         }
     }
@@ -572,21 +589,8 @@ struct PanelLL {
         asm volatile("" : "+v"(lane));
         const bool active = lane < ncols;
         HSMA_GLOBAL double *__restrict__ bc = (HSMA_GLOBAL double *)(B + ES * (int64_t)(active ? lane : 0) * ldb);
-
-        double rr = 1.0, ri = 0.0;
-        if (!UNIT && lane < m) {
-            const HSMA_GLOBAL double *d = (const HSMA_GLOBAL double *)(A + ES * ((int64_t)lane + (int64_t)lane * lda));
-            if (CX) {
-                const double vx = d[0], vy = d[1];
-                const double den = vx * vx + vy * vy;
-                rr = vx / den;
-                ri = -vy / den;
-            } else {
-                rr = 1.0 / d[0];
-            }
-        }
         __shared__ double Lp[ES * (COALESCED_STORE && PANEL < RB * 64 ? RB * 64 : PANEL)];
-        block<0>(A, lda, Lp, bc, active, (HSMA_GLOBAL double *)B, ldb, ncols, m, lane, rr, ri, alpha);
+        block<0>(A, lda, Lp, bc, active, (HSMA_GLOBAL double *)B, ldb, ncols, m, lane, alpha);
         __syncthreads();  // LDS is reused by the next item of a persistent wave
     }
 };
