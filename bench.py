@@ -203,14 +203,29 @@ def run_single_problem(args, torch, hs, cfg):
     for _ in range(args.warmup):
         hs.trsm(Ld, Bd, alpha, block_size=args.ib)
     torch.cuda.synchronize()
-    hs.profile_begin()
-    torch.cuda.synchronize()
-    ts = time.perf_counter()
-    for _ in range(args.steps):
-        hs.trsm(Ld, Bd, alpha, block_size=args.ib)
-    torch.cuda.synchronize()
-    te = time.perf_counter()
-    prof = hs.profile_end()
+    if rep["path"] != 2:
+        # A lone small solve is bound by call and launch latency: time it
+        # without the phase profiler's events, then profile a second pass of
+        # the same length for the kernel's own duration.
+        ts = time.perf_counter()
+        for _ in range(args.steps):
+            hs.trsm(Ld, Bd, alpha, block_size=args.ib)
+        torch.cuda.synchronize()
+        te = time.perf_counter()
+        hs.profile_begin()
+        for _ in range(args.steps):
+            hs.trsm(Ld, Bd, alpha, block_size=args.ib)
+        torch.cuda.synchronize()
+        prof = hs.profile_end()
+    else:
+        hs.profile_begin()
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        for _ in range(args.steps):
+            hs.trsm(Ld, Bd, alpha, block_size=args.ib)
+        torch.cuda.synchronize()
+        te = time.perf_counter()
+        prof = hs.profile_end()
     ms = (te - ts) * 1e3 / args.steps
     fl = W.flops(m, n, cx)
 
