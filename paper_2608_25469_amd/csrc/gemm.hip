@@ -637,11 +637,6 @@ int gemm_grouped_tile(GemmRole role, int max_m, int max_n, int *bm, int *bn) {
     return 1;
 }
 
-int gemm_grouped_bucket(GemmRole role, int n) {
-    if (role == GemmRole::Leaf) return 0;
-    return n <= 32 ? 0 : (n <= 64 ? 1 : 2);
-}
-
 hsma_status launch_gemm_grouped(bool cplx_, GemmRole role, int bm, int bn, const GemmParams *descs,
                                 int nd, int64_t total_tiles, double flops, hipStream_t s) {
     if (nd <= 0 || total_tiles <= 0) return HSMA_SUCCESS;

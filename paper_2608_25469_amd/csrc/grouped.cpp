@@ -280,27 +280,11 @@ hsma_status grouped_blocked(const hsma_problem *probs, int64_t count, hipStream_
             }
     }
 
-    // Split each product launch by column-count bucket (narrow right-hand
-    // sides get narrow tiles); the pieces stay in order on the stream.
-    {
-        std::vector<Launch> split;
-        for (Launch &l : launches) {
-            if (l.kind == 1) {
-                split.push_back(std::move(l));
-                continue;
-            }
-            Launch part[3];
-            for (int b = 0; b < 3; ++b) {
-                part[b].kind = 0;
-                part[b].cx = l.cx;
-                part[b].role = l.role;
-            }
-            for (const Gemm &g : l.gemms) part[gemm_grouped_bucket(l.role, g.g.N)].gemms.push_back(g);
-            for (int b = 0; b < 3; ++b)
-                if (!part[b].gemms.empty()) split.push_back(std::move(part[b]));
-        }
-        launches.swap(split);
-    }
+    // Each step's products share one launch whatever their widths: the tile
+    // shape follows the widest.  Separate launches for narrow right-hand
+    // sides would add kernel boundaries to the dependent chain, and on a
+    // served mix (n log-uniform in [1, 512]) cost more than the columns the
+    // wide tiles leave idle.
 
     // Tile shapes, grid sizes and the descriptor image.
     size_t img_bytes = 0;

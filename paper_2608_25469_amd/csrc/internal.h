@@ -115,9 +115,6 @@ struct GemmParams {
 // max_m real-view rows and max_n columns (leaves need one tile to span all
 // rows); 0 if unsupported.
 int gemm_grouped_tile(GemmRole role, int max_m, int max_n, int *bm, int *bn);
-// Products of one grouped step are split into launches by column count;
-// returns the bucket (0, 1, 2) of a product with n columns.
-int gemm_grouped_bucket(GemmRole role, int n);
 // Launch over nd descriptors already in device memory (tile0 / tiles_m /
 // tiles_n filled for the shape gemm_grouped_tile returned); total_tiles is
 // the grid size.  flops is for the phase profiler.
