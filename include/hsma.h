@@ -292,10 +292,10 @@ hsma_status hsma_generate_inputs(hsma_dtype dtype, int64_t m, int64_t n, uint64_
  *   - admits pending requests strictly in arrival order while the HBM budget
  *     and the in-flight limit allow,
  *   - launches each admission round by size class (m <= 64; 64 < m <= 512;
- *     m > 512), each class as one batched solve (hsma_trsm_batched's work,
- *     all of it on the class's stream) with its own completion event: the
- *     small class on the queue's small stream, the two
- *     blocked classes round-robin over the queue's other streams.  Synthetic
+ *     m > 512; the last two split by data type), each class as one batched
+ *     solve (hsma_trsm_batched's work, all of it on the class's stream) with
+ *     its own completion event: the small class on the queue's small stream,
+ *     the four blocked classes round-robin over the queue's other streams.  Synthetic
  *     inputs of a class are drawn in one launch on the class's stream first.
  * A request's footprint is its blocked-path workspace (a 4 KiB descriptor
  * share for small requests) plus, for synthetic requests, its L and B.

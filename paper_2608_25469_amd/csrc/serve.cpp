@@ -9,10 +9,10 @@
 //      rejected at submit, so the head of the queue always fits once the
 //      work ahead of it retires),
 //   3. launches what it admitted by size class -- m <= 64, 64 < m <= 512,
-//      m > 512 -- each class as one batched call (persistent small-solve
-//      groups, or grouped blocked launches that advance all of the class's
-//      problems together) on its own stream, the two blocked classes
-//      round-robin over the queue's streams,
+//      m > 512, the last two split by data type -- each class as one batched
+//      call (persistent small-solve groups, or grouped blocked launches that
+//      advance all of the class's problems together) on its own stream, the
+//      four blocked classes round-robin over the queue's streams,
 // so requests arriving while others run reach the device as soon as slots
 // and memory free up, and their work overlaps on the GPU.
 //
@@ -175,11 +175,17 @@ void finish(hsma_queue *q, Req *r, double t, hsma_status st) {
     r->held = keep_bytes;
 }
 
-// Size classes of one admission round.  Each class is one batched call on
-// its own stream with its own completion event, so a round's small solves do
-// not wait for its largest blocked solve.
-int size_class(const hsma_problem &p) { return p.m <= 64 ? 0 : (p.m <= 512 ? 1 : 2); }
-constexpr int kClasses = 3;
+// Size classes of one admission round: m <= 64, then 64 < m <= 512 and
+// m > 512, each of these two split by data type.  Each class is one batched
+// call on its own stream with its own completion event, so a round's small
+// solves do not wait for its largest blocked solve, and the real and complex
+// blocked chains of a round (separate launches at every step) run side by
+// side instead of interleaved on one stream.
+int size_class(const hsma_problem &p) {
+    if (p.m <= 64) return 0;
+    return (p.m <= 512 ? 1 : 3) + (p.dtype == HSMA_C64F ? 1 : 0);
+}
+constexpr int kClasses = 5;
 
 // Enqueue the admitted requests (HIP backend).  Called without the lock.
 void launch_admitted(hsma_queue *q, std::vector<Req *> &adm) {
