@@ -207,8 +207,8 @@ typedef struct {
  * diagonal kinds and alphas may all differ.  Each problem is validated with
  * the hsma_trsm rules first; on the first invalid one its index goes to
  * *first_bad (if non-NULL), its status is returned and nothing is enqueued.
- * Problems with m <= 64 run in persistent grouped launches (one per data
- * type and diagonal kind, longest problems first); the rest take the
+ * Problems with m <= 64 run in grouped launches (one per data type and
+ * diagonal kind, one workgroup per 64-column panel, longest first); the rest take the
  * blocked path grouped: every problem keeps the schedule (I_B, inversions,
  * recursion) it gets alone, so its result is bit-for-bit the same, but the
  * k-th operation of all of them shares one launch.  Both parts are forked
@@ -224,7 +224,7 @@ hsma_status hsma_trsm_batched(const hsma_problem *probs, int64_t count, int64_t 
  * to device memory owned by the plan (synchronously, on the current device).
  * execute enqueues the whole batch on `stream` (same device as create; no
  * host-to-device copy).  Executions of one plan must not overlap in time
- * (they share the plan's work counters).  destroy frees the plan after the
+ * (they solve in place in the same B).  destroy frees the plan after the
  * caller has synchronised with its last execution.
  */
 typedef struct hsma_batch_plan hsma_batch_plan;

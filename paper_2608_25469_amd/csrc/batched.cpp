@@ -2,12 +2,12 @@
 // work, Sec. 6).
 //
 // Problems with m <= 64 become work items -- one per 64-column panel -- of
-// the persistent small-solve kernel.  Items are grouped by (data type,
-// diagonal kind); inside a group items are ordered by decreasing cost
-// (longest processing time first).  The item table, with a zeroed work
-// counter and exit counter per group in front, is uploaded in one copy; the group
-// launches are forked onto library-owned streams so they overlap on the
-// device, and joined back into the caller's stream.  Problems with m > 64
+// the small-solve kernel, one workgroup per item.  Items are grouped by (data
+// type, diagonal kind); inside a group items are ordered by decreasing cost
+// (longest processing time first; the hardware starts workgroups in that
+// order).  The item table is uploaded in one copy; the group launches are
+// forked onto library-owned streams so they overlap on the device, and
+// joined back into the caller's stream.  Problems with m > 64
 // take the grouped blocked path (grouped.cpp) on one more forked stream.
 
 #include <algorithm>
@@ -31,12 +31,8 @@ hsma_status trsm_impl(hsma_diag diag, int64_t m, int64_t n, const void *alpha, c
 hsma_status grouped_blocked(const hsma_problem *probs, int64_t count, hipStream_t s);
 
 // From small_d.hip / small_z.hip
-hsma_status launch_small_group_d(bool unit, int nch, const void *items, int count,
-                                 int32_t *counter, int32_t *done, int wgs, hipStream_t s);
-hsma_status launch_small_group_z(bool unit, int nch, const void *items, int count,
-                                 int32_t *counter, int32_t *done, int wgs, hipStream_t s);
-int small_group_occupancy_d(bool unit, int nch);
-int small_group_occupancy_z(bool unit, int nch);
+hsma_status launch_small_group_d(bool unit, int nch, const void *items, int count, hipStream_t s);
+hsma_status launch_small_group_z(bool unit, int nch, const void *items, int count, hipStream_t s);
 size_t small_item_bytes_d();
 
 namespace {
@@ -52,14 +48,11 @@ struct Item {
 
 constexpr int kGroups = 2 * 2 * 8;  // complex x unit x kernel instance (one used per pair)
 constexpr int kForkStreams = 8;
-constexpr size_t kHeader = 256;     // kGroups int32 work counters, then kGroups exit counters
-static_assert(2 * kGroups * sizeof(int32_t) <= kHeader, "counters fit the header");
 
-// Every small item of a (data type, diagonal kind) runs in one persistent
-// launch of the 64-row instance: its left-looking walk skips the 16-row
-// blocks past each item's m, so the work still follows m, and one launch
-// keeps the whole GPU on one longest-first queue instead of several
-// launches competing for it.
+// Every small item of a (data type, diagonal kind) runs in one launch of the
+// 64-row instance: its left-looking walk skips the 16-row blocks past each
+// item's m, so the work still follows m, and one launch keeps the whole GPU
+// on one longest-first queue instead of several launches competing for it.
 int group_of(bool cx, bool unit, int m) {
     (void)m;
     return ((cx ? 1 : 0) * 2 + (unit ? 1 : 0)) * 8 + 7;
@@ -68,7 +61,6 @@ int group_of(bool cx, bool unit, int m) {
 struct DevicePool {
     bool init = false;
     hipStream_t fork[kForkStreams] = {};
-    int occ[kGroups] = {};
     std::mutex mu;
     // Pinned staging buffers for descriptor uploads.  A buffer is reusable
     // once the copy out of it has finished (its event); the pool grows up to
@@ -85,7 +77,7 @@ struct DevicePool {
 constexpr size_t kMaxStages = 64;
 DevicePool g_pools[64];
 
-hsma_status pool_for(DevicePool **out, int *cus) {
+hsma_status pool_for(DevicePool **out) {
     DeviceInfo di;
     HSMA_TRY(device_info(&di));
     DevicePool &p = g_pools[di.device];
@@ -93,24 +85,18 @@ hsma_status pool_for(DevicePool **out, int *cus) {
     if (!p.init) {
         for (int i = 0; i < kForkStreams; ++i)
             HSMA_HIP(hipStreamCreateWithFlags(&p.fork[i], hipStreamNonBlocking));
-        for (int g = 0; g < kGroups; ++g) {
-            const bool cx = g >= 16, unit = (g / 8) % 2;
-            const int nch = g % 8 + 1;
-            p.occ[g] = cx ? small_group_occupancy_z(unit, nch) : small_group_occupancy_d(unit, nch);
-        }
         p.init = true;
     }
     *out = &p;
-    *cus = di.num_cus;
     return HSMA_SUCCESS;
 }
 
 }  // namespace
 
-// The device-resident part of a batch: item table with counters, group
-// extents, and the problems that take the blocked path.
+// The device-resident part of a batch: item table, group extents, and the
+// problems that take the blocked path.
 struct BatchTable {
-    void *dev = nullptr;  // kHeader bytes of counters, then items
+    void *dev = nullptr;  // items, grouped and sorted
     size_t bytes = 0;
     int start[kGroups] = {}, count[kGroups] = {};
     std::vector<hsma_problem> large;
@@ -134,7 +120,7 @@ static hsma_status check_all(const hsma_problem *probs, int64_t count, int64_t *
     return HSMA_SUCCESS;
 }
 
-// Host image of the table: counters (zero) then items grouped and sorted.
+// Host image of the table: items grouped and sorted.
 static void build_image(const hsma_problem *probs, int64_t count, BatchTable *t,
                         std::vector<unsigned char> *img) {
     std::vector<Item> groups[kGroups];
@@ -165,7 +151,7 @@ static void build_image(const hsma_problem *probs, int64_t count, BatchTable *t,
     }
     size_t n_items = 0;
     for (int g = 0; g < kGroups; ++g) n_items += groups[g].size();
-    img->assign(kHeader + n_items * sizeof(Item), 0);
+    img->assign(n_items * sizeof(Item), 0);
     size_t pos = 0;
     for (int g = 0; g < kGroups; ++g) {
         std::vector<size_t> order(groups[g].size());
@@ -175,7 +161,7 @@ static void build_image(const hsma_problem *probs, int64_t count, BatchTable *t,
         t->start[g] = (int)pos;
         t->count[g] = (int)order.size();
         for (size_t i : order) {
-            std::memcpy(img->data() + kHeader + pos * sizeof(Item), &groups[g][i], sizeof(Item));
+            std::memcpy(img->data() + pos * sizeof(Item), &groups[g][i], sizeof(Item));
             ++pos;
         }
     }
@@ -201,8 +187,7 @@ static hsma_status run_large(const std::vector<hsma_problem> &large, hipStream_t
 // fork, the launches are spread over library streams and joined back.
 static hsma_status run_table(const BatchTable &t, hipStream_t s, bool fork = true) {
     DevicePool *pool;
-    int cus = 0;
-    HSMA_TRY(pool_for(&pool, &cus));
+    HSMA_TRY(pool_for(&pool));
     int ngroups = 0;
     for (int g = 0; g < kGroups; ++g) ngroups += t.count[g] > 0;
     if (!t.large.empty()) ngroups += 1;
@@ -224,14 +209,12 @@ static hsma_status run_table(const BatchTable &t, hipStream_t s, bool fork = tru
             if (fs != s) HSMA_HIP(hipStreamWaitEvent(fs, fork_ev, 0));
             const bool cx = g >= 16, unit = (g / 8) % 2;
             const int nch = g % 8 + 1;
-            const int wgs = std::max(1, std::min(t.count[g], pool->occ[g] * cus));
             const unsigned char *base = static_cast<const unsigned char *>(t.dev);
-            const void *items = base + kHeader + (size_t)t.start[g] * sizeof(Item);
-            int32_t *counter = reinterpret_cast<int32_t *>(const_cast<unsigned char *>(base)) + g;
+            const void *items = base + (size_t)t.start[g] * sizeof(Item);
             {
                 ProfScope prof(HSMA_PHASE_SMALL, 0.0, fs);
-                st = cx ? launch_small_group_z(unit, nch, items, t.count[g], counter, counter + kGroups, wgs, fs)
-                        : launch_small_group_d(unit, nch, items, t.count[g], counter, counter + kGroups, wgs, fs);
+                st = cx ? launch_small_group_z(unit, nch, items, t.count[g], fs)
+                        : launch_small_group_d(unit, nch, items, t.count[g], fs);
             }
             if (fs != s) {
                 hipEvent_t j;
@@ -267,8 +250,7 @@ static hsma_status run_table(const BatchTable &t, hipStream_t s, bool fork = tru
 hsma_status upload_async(const void *host, size_t bytes, void *dev, hipStream_t s) {
     if (bytes == 0) return HSMA_SUCCESS;
     DevicePool *pool;
-    int cus;
-    HSMA_TRY(pool_for(&pool, &cus));
+    HSMA_TRY(pool_for(&pool));
     std::lock_guard<std::mutex> lk(pool->mu);
     auto idle = [](DevicePool::Stage &x) {
         if (!x.used) return true;
@@ -326,7 +308,7 @@ hsma_status trsm_batched_serial(const hsma_problem *probs, int64_t count, hipStr
     BatchTable t;
     std::vector<unsigned char> img;
     build_image(probs, count, &t, &img);
-    if (img.size() > kHeader) {
+    if (!img.empty()) {
         HSMA_TRY(ws_alloc(&t.dev, img.size(), s));
         t.bytes = img.size();
         hsma_status st = upload(img, t.dev, s);
@@ -356,7 +338,7 @@ hsma_status hsma_trsm_batched(const hsma_problem *probs, int64_t count, int64_t 
     BatchTable t;
     std::vector<unsigned char> img;
     build_image(probs, count, &t, &img);
-    if (img.size() > kHeader) {
+    if (!img.empty()) {
         HSMA_TRY(ws_alloc(&t.dev, img.size(), s));
         t.bytes = img.size();
         hsma_status st = upload(img, t.dev, s);
@@ -378,7 +360,7 @@ hsma_status hsma_batch_plan_create(const hsma_problem *probs, int64_t count, int
     std::vector<unsigned char> img;
     build_image(probs, count, &p->table, &img);
     hipError_t e = hipGetDevice(&p->device);
-    if (e == hipSuccess && img.size() > kHeader) {
+    if (e == hipSuccess && !img.empty()) {
         e = hipMalloc(&p->table.dev, img.size());
         if (e == hipSuccess) e = hipMemcpy(p->table.dev, img.data(), img.size(), hipMemcpyHostToDevice);
         p->table.bytes = img.size();
@@ -399,8 +381,6 @@ hsma_status hsma_batch_plan_execute(hsma_batch_plan *plan, hsma_stream_t stream)
     HSMA_HIP(hipGetDevice(&dev));
     if (dev != plan->device) return HSMA_INVALID_VALUE;
     hipStream_t s = static_cast<hipStream_t>(stream);
-    // The counters are zero: the upload wrote them so, and every completed
-    // group launch returns its own to zero.
     return run_table(plan->table, s);
 }
 

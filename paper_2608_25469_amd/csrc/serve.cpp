@@ -10,7 +10,7 @@
 //      work ahead of it retires),
 //   3. launches what it admitted by size class -- m <= 64, 64 < m <= 512,
 //      m > 512, the last two split by data type -- each class as one batched
-//      call (persistent small-solve groups, or grouped blocked launches that
+//      call (grouped small-solve launches, or grouped blocked launches that
 //      advance all of the class's problems together) on its own stream, the
 //      four blocked classes round-robin over the queue's streams,
 // so requests arriving while others run reach the device as soon as slots

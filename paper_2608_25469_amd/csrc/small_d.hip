@@ -25,21 +25,6 @@ void small_launch(int nch, dim3 grid, const SmallItem &one, const SmallGroup &gr
 }
 
 template <bool UNIT>
-const void *small_kernel_ptr(int nch) {
-    switch (nch) {
-        case 1: return (const void *)hsma_small_solve<false, 1, UNIT>;
-        case 2: return (const void *)hsma_small_solve<false, 2, UNIT>;
-        case 3: return (const void *)hsma_small_solve<false, 3, UNIT>;
-        case 4: return (const void *)hsma_small_solve<false, 4, UNIT>;
-        case 5: return (const void *)hsma_small_solve<false, 5, UNIT>;
-        case 6: return (const void *)hsma_small_solve<false, 6, UNIT>;
-        case 7: return (const void *)hsma_small_solve<false, 7, UNIT>;
-        case 8: return (const void *)hsma_small_solve<false, 8, UNIT>;
-    }
-    return nullptr;
-}
-
-template <bool UNIT>
 hsma_status inv_t(int m, int base, int ib, const double *A, int64_t lda, double *W,
                   hipStream_t s) {
     dim3 grid((m + base - 1) / base), block(64);
@@ -92,7 +77,7 @@ hsma_status launch_small_d(bool unit, int m, int64_t n, cplx alpha, const double
     const int64_t panels = (n + 63) / 64;
     if (panels > 0x7fffffff || n > 0x7fffffff) return HSMA_INVALID_SIZE;
     SmallItem one{A, B, lda, ldb, m, (int32_t)n, alpha.re, alpha.im};
-    SmallGroup none{nullptr, 0, nullptr, nullptr};
+    SmallGroup none{nullptr, 0};
     const int nch = (m + 7) / 8;
     if (nch < 1 || nch > 8) return HSMA_INVALID_SIZE;
     if (unit) small_launch<true>(nch, dim3((unsigned)panels), one, none, s);
@@ -101,28 +86,16 @@ hsma_status launch_small_d(bool unit, int m, int64_t n, cplx alpha, const double
     return HSMA_SUCCESS;
 }
 
-// Persistent grouped launch over `grp` (device table) with `wgs` workgroups;
-// counter and done start at zero and are zero again when the launch ends.
+// Grouped launch over `grp` (device table): one workgroup per item.
 hsma_status launch_small_group_d(bool unit, int nch, const void *grp_items, int count,
-                                    int32_t *counter, int32_t *done, int wgs, hipStream_t s) {
+                                    hipStream_t s) {
     SmallItem one{};
-    SmallGroup grp{static_cast<const SmallItem *>(grp_items), count, counter, done};
-    if (nch < 1 || nch > 8 || wgs < 1) return HSMA_INVALID_SIZE;
-    if (unit) small_launch<true>(nch, dim3(wgs), one, grp, s);
-    else small_launch<false>(nch, dim3(wgs), one, grp, s);
+    SmallGroup grp{static_cast<const SmallItem *>(grp_items), count};
+    if (nch < 1 || nch > 8 || count < 1) return HSMA_INVALID_SIZE;
+    if (unit) small_launch<true>(nch, dim3((unsigned)count), one, grp, s);
+    else small_launch<false>(nch, dim3((unsigned)count), one, grp, s);
     HSMA_HIP(hipGetLastError());
     return HSMA_SUCCESS;
-}
-
-// Resident wavefronts per CU of the grouped kernel instance for row bound 8 * nch.
-int small_group_occupancy_d(bool unit, int nch) {
-    const void *k = unit ? small_kernel_ptr<true>(nch) : small_kernel_ptr<false>(nch);
-    int blocks = 0;
-    if (!k || hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k, 64, 0) != hipSuccess) {
-        (void)hipGetLastError();
-        return 4;
-    }
-    return blocks > 0 ? blocks : 1;
 }
 
 hsma_status launch_inv_base_d(bool unit, int m, int base, int ib, const double *A,
