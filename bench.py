@@ -337,7 +337,7 @@ def run_batched(args, torch, hs, cfg):
     bytes_per_launch = byts / launches
     ach = bytes_per_launch / (avg_launch_ms * 1e-3) / 1e9
     traffic = measured_traffic("small_solve_batched10000_traffic", SMALL_SOURCES, count == cfg["count"])
-    roof = {"bound": "hbm", "kernel": "hsma_small_solve (grouped, persistent)",
+    roof = {"bound": "hbm", "kernel": "hsma_small_solve (grouped, one workgroup per item)",
             "achieved": round(ach, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic,
             "avg_launch_ms": avg_launch_ms, "launches_per_step": launches,
