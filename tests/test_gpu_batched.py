@@ -152,3 +152,33 @@ def test_grouped_blocked_bitwise_equal_to_single():
         if B.shape[0] <= 1100:
             ref = oracle.solve(L, B, a, unit=u)
             assert oracle.rel_err_fro(X, ref) <= 1e-12
+
+
+def test_more_items_than_one_grid_row():
+    """70 000 tiny problems (more than 65 535 workgroups in one launch, one
+    per item).  Inputs are small integers with diagonals in {1, 2, 4}, so
+    every solution is exact in FP64 and is checked bit for bit against the
+    2 x 2 forward substitution written out."""
+    count = 70_000
+    rng = np.random.default_rng(17)
+    l00 = rng.choice([1.0, 2.0, 4.0], count)
+    l11 = rng.choice([1.0, 2.0, 4.0], count)
+    l10 = rng.integers(-3, 4, count).astype(np.float64)
+    b0 = rng.integers(-8, 9, count).astype(np.float64)
+    b1 = rng.integers(-8, 9, count).astype(np.float64)
+    # Problem i: L column-major 2 x 2 at offset 4i (lda 2), B 2 x 1 at offset 2i.
+    Lh = np.zeros((count, 4))
+    Lh[:, 0], Lh[:, 1], Lh[:, 3] = l00, l10, l11
+    Lh[:, 2] = 99.0  # upper triangle: never read as a coefficient
+    Bh = np.stack([b0, b1], axis=1)
+    Ld = torch.from_numpy(Lh.reshape(-1)).cuda()
+    Bd = torch.from_numpy(Bh.reshape(-1)).cuda()
+    lp, bp = Ld.data_ptr(), Bd.data_ptr()
+    probs = [hs.Problem(0, 0, 2, 1, 1.0, 0.0, lp + 32 * i, 2, bp + 16 * i, 2) for i in range(count)]
+    hs.trsm_batched(probs)
+    torch.cuda.synchronize()
+    X = Bd.cpu().numpy().reshape(count, 2)
+    x0 = b0 * (1.0 / l00)
+    x1 = (b1 - l10 * x0) * (1.0 / l11)
+    assert np.array_equal(X[:, 0], x0)
+    assert np.array_equal(X[:, 1], x1)
