@@ -52,10 +52,6 @@ __device__ __forceinline__ double readlane_d(double v, int lane) {
     return __hiloint2double(hi, lo);
 }
 
-struct alignas(16) dpair {
-    double x, y;
-};
-
 // ---------------------------------------------------------------------------
 // Broadcast of L.  Every lane needs every coefficient l_ik (lane j works on
 // column j).  Column k of L is loaded with vector loads into NQ = ceil(MAXM/16)
@@ -72,11 +68,6 @@ struct alignas(16) dpair {
 template <int N>
 __device__ __forceinline__ double bcast16(double v) {
     return __builtin_amdgcn_mov_dpp(v, 0x150 + N, 0xf, 0xf, false);  // row_newbcast:N
-}
-
-template <int R>
-__device__ __forceinline__ double bcast_row(double v) {
-    return bcast16<R>(v);
 }
 
 // Static dispatch of row_newbcast on a compile-time row number.
