@@ -309,7 +309,7 @@ typedef struct {
                                  takes sim_fixed_ns + flops / sim_flops_per_ns
                                  of modelled time on its stream (flops = m^2 n,
                                  x4 for complex); for tests of the policy */
-    int32_t n_streams;        /* streams for large requests (0 = 4) */
+    int32_t n_streams;        /* streams for large requests (0 = 8) */
     int32_t max_inflight;     /* admitted, unfinished requests (0 = 8192) */
     int32_t poll_us;          /* completion poll period while work runs (0 = 20) */
     uint64_t hbm_budget_bytes;/* summed footprint limit (0 = 32 GiB) */
