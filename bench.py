@@ -642,7 +642,8 @@ def run_serving(args, torch, hs):
 
 def run_headline(args, torch, hs, names):
     """The rest of the headline metric in the same run: the large DTRSM and
-    ZTRSM solves and the serving run (each failure is reported, not fatal)."""
+    ZTRSM solves, a lone small solve, graph replay, mixed precision and the
+    serving run (each failure is reported, not fatal)."""
     import copy
     out = {}
     sub = copy.copy(args)
@@ -661,6 +662,16 @@ def run_headline(args, torch, hs, names):
             out[key] = {"error": repr(e)}
         torch.cuda.empty_cache()
         hs.workspace_release()
+    try:
+        # A lone small solve: call latency against rocBLAS's.
+        one = copy.copy(sub)
+        one.workload, one.steps, one.warmup = "single", 200, 20
+        r = run_single_problem(one, torch, hs, dict(W.SINGLE_SMALL))
+        out["single"] = {"workload": names["single"], "ms_per_call": r["ms_per_step"],
+                         "kernel_ms": r["phases"]["small"]["ms_per_step"],
+                         "rocblas": r.get("rocblas"), "parity": r.get("parity")}
+    except Exception as e:
+        out["single"] = {"error": repr(e)}
     try:
         out["graph"] = run_graph(sub, torch, hs)
     except Exception as e:
