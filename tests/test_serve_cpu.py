@@ -240,3 +240,22 @@ def test_config_validation():
     cfg = hs.QueueConfig(hs.BACKEND_SIMULATED, -1, 0, 0, 0, 0.0, 0.0)
     assert hs.lib().hsma_queue_create(ctypes.byref(cfg), ctypes.byref(h)) == 1
     assert hs.lib().hsma_queue_create(ctypes.byref(cfg), None) == 3
+
+
+def test_blocked_classes_split_by_size_and_data_type():
+    """One admission round with a real and a complex request of each blocked
+    size class: four class launches on four different streams, each modelled
+    as fixed + its own flops / rate, so each request finishes at its own
+    class's modelled time (a launch shared by the real and the complex
+    request of a class would finish both at the summed time)."""
+    rate, fixed = 0.05, 1_000.0
+    shapes = [(200, 10, False), (200, 10, True), (600, 10, False), (600, 10, True)]
+    with sim_queue(rate_flops_per_ns=rate, fixed_ns=fixed, n_streams=8) as q:
+        tk = q.submit([dev_req(m, n, cx=cx) for m, n, cx in shapes])
+        infos = wait_all(q, tk)
+    assert all(i["status"] == 0 and i["path"] == 2 for i in infos)
+    assert len({i["t_admit_ns"] for i in infos}) == 1          # one round
+    for (m, n, cx), i in zip(shapes, infos):
+        model = fixed + m * m * n * (4.0 if cx else 1.0) / rate
+        took = i["t_done_ns"] - i["t_admit_ns"]
+        assert model * 0.999 <= took <= model + 2 * MS, (m, cx, took, model)
