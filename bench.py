@@ -23,7 +23,7 @@ Single workloads (--workload):
   serving        open-loop Poisson arrivals (--rate per s, --duration s) of
                  requests with m, n log-uniform in [8, 4096] x [1, 512], 30 %
                  complex, alpha ~ U(-2, 2), inputs drawn on the device from
-                 Philox keys, 32 GiB budget; reports p50/p99 latency from
+                 Philox keys, 96 GiB budget; reports p50/p99 latency from
                  scheduled arrival to completion and solves/s
 
 Prints one JSON line: metric/value, the roofline of the dominant kernel
@@ -71,6 +71,8 @@ def parse():
     ap.add_argument("--rate", type=float, default=20000.0, help="serving: arrivals per second")
     ap.add_argument("--duration", type=float, default=12.0, help="serving: seconds of arrivals")
     ap.add_argument("--streams", type=int, default=0, help="serving: queue streams (0 = default)")
+    ap.add_argument("--budget-gib", type=float, default=0.0,
+                    help="serving: HBM admission budget in GiB (0 = the library's 96 GiB)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="fill a 1 GiB tensor and copy it first (reference kernels of known size for counter runs)")
     return ap.parse_args()
@@ -532,7 +534,8 @@ def run_serving(args, torch, hs):
     log(f"serving: {N} requests over {duration:.0f} s at {rate:.0f}/s, "
         f"{total_flops / duration / 1e12:.2f} TFLOP/s offered")
     L = hs.lib()
-    q = hs.Queue(n_streams=args.streams)
+    budget = int(args.budget_gib * 2**30) if args.budget_gib > 0 else 0
+    q = hs.Queue(n_streams=args.streams, hbm_budget_bytes=budget)
     # Warm-up (first launches of every kernel family, memory pool growth).
     wk = [hs.request(m, n, 1.0, complex_=cx, key=W.serving_key(99, k))
           for k, (m, n, cx) in enumerate([(m, n, cx) for m in (8, 40, 64, 100, 300, 1000, 3000)
@@ -629,7 +632,7 @@ def run_serving(args, torch, hs):
                     "latency_window": f"arrivals after the first {warm_s:.0f} s",
                     "offered_per_s": rate, "requests": N, "completed": completed, "failed": failed,
                     "rejected": s["rejected"], "peak_budget_bytes": s["bytes_peak"],
-                    "budget_bytes": 32 << 30, "saturated": saturated,
+                    "budget_bytes": budget or 96 << 30, "saturated": saturated,
                     "drain_after_last_arrival_s": round(backlog_s, 3),
                     "admission_rounds": s["rounds"], "scheduler_launch_ms": round(s["launch_ms"], 1),
                     "served_tflops": round(total_flops / span / 1e12, 3)},

@@ -312,7 +312,7 @@ typedef struct {
     int32_t n_streams;        /* streams for large requests (0 = 8) */
     int32_t max_inflight;     /* admitted, unfinished requests (0 = 8192) */
     int32_t poll_us;          /* completion poll period while work runs (0 = 20) */
-    uint64_t hbm_budget_bytes;/* summed footprint limit (0 = 32 GiB) */
+    uint64_t hbm_budget_bytes;/* summed footprint limit (0 = 96 GiB) */
     double sim_flops_per_ns;  /* simulated rate (<= 0: 40000, i.e. 40 TFLOP/s) */
     double sim_fixed_ns;      /* simulated per-launch latency */
 } hsma_queue_config;
