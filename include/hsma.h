@@ -126,7 +126,9 @@ typedef struct {
                              -1 = stop as soon as the backward error is
                              <= refine_tol (at most 4 steps) */
     int32_t want_backward_error; /* 1: compute the normwise backward error of
-                             the returned X (an FP64 residual on the GPU) */
+                             the returned X from an FP64 residual on the GPU,
+                             formed by one triangular product whose order of
+                             summation is independent of the solve's */
     int32_t use_graph;    /* 1: run the blocked schedule as a HIP graph captured
                              on first use and replayed while (dtype, diag, m, n,
                              A, lda, B, ldb, alpha, I_B, precision) repeat; the
@@ -152,7 +154,8 @@ typedef struct {
  * and error behaviour.  opts may be NULL (all defaults); report may be NULL.
  * Unknown option values give HSMA_INVALID_VALUE; forcing the small kernel
  * with m > 64 gives HSMA_NOT_SUPPORTED; HSMA_PREC_MIXED with complex data
- * gives HSMA_NOT_SUPPORTED.
+ * gives HSMA_NOT_SUPPORTED.  Refinement and the backward error work for both
+ * data types (complex: the modulus in every row sum and |alpha|).
  * Asynchronous on `stream` unless a backward error is needed
  * (want_backward_error = 1 or refine_steps = -1): then the call waits for the
  * stream before returning, because the value decides what happens next.
@@ -312,7 +315,7 @@ typedef struct {
     int32_t n_streams;        /* streams for large requests (0 = 8) */
     int32_t max_inflight;     /* admitted, unfinished requests (0 = 8192) */
     int32_t poll_us;          /* completion poll period while work runs (0 = 20) */
-    uint64_t hbm_budget_bytes;/* summed footprint limit (0 = 96 GiB) */
+    uint64_t hbm_budget_bytes;/* summed footprint limit (0 = 32 GiB) */
     double sim_flops_per_ns;  /* simulated rate (<= 0: 40000, i.e. 40 TFLOP/s) */
     double sim_fixed_ns;      /* simulated per-launch latency */
 } hsma_queue_config;
@@ -323,10 +326,16 @@ typedef struct {
                                  lda = ldb = m and fills them with
                                  hsma_generate_inputs under `key`) */
     int32_t input;            /* hsma_input_kind */
-    int32_t release_on_completion; /* synthetic only: 1 frees L and B as soon
-                                 as the solve finishes (load generation);
-                                 0 keeps them, counted against the budget,
-                                 until hsma_queue_release */
+    int32_t release_on_completion; /* 0: a synthetic request keeps L and X,
+                                 counted against the budget, and every request
+                                 keeps its record until hsma_queue_release;
+                                 1: a synthetic request's L and B are freed as
+                                 soon as the solve finishes, the record stays
+                                 until released;
+                                 2 (fire and forget, for load generation): as
+                                 1, and the record is dropped too -- poll, wait
+                                 and release then give HSMA_NOT_FOUND; the
+                                 request still enters the statistics */
     uint64_t key;             /* Philox key of a synthetic request */
     double t_arrival_ns;      /* arrival time on hsma_clock_ns()'s clock for
                                  the latency figure; <= 0 means "now" (an
@@ -343,15 +352,32 @@ typedef struct {
     int64_t lda, ldb;
 } hsma_request_info;
 
+/* Latency (arrival to completion) of the completed requests in the
+ * statistics window.  Kept as a histogram of 64 logarithmic bins per doubling
+ * from 1 us (and one bin below): percentile q is the bin holding the sample
+ * of rank round(q (count - 1)), reported as the bin's geometric midpoint
+ * clamped to the observed minimum and maximum, so it is within 0.6 % of the
+ * exact order statistic.  max and mean are exact.  Memory and the cost of a
+ * statistics call do not grow with the number of requests. */
+typedef struct {
+    int64_t count;
+    double p50_ns, p99_ns, max_ns, mean_ns;
+} hsma_latency_summary;
+
+/* Size classes of the per-class latency: m <= 64, 64 < m <= 512, m > 512. */
+#define HSMA_LATENCY_CLASSES 3
+
 typedef struct {
     int64_t submitted, rejected, completed, failed, pending, inflight;
     uint64_t bytes_in_use, bytes_peak;  /* budget accounting */
-    double p50_ns, p99_ns, max_ns, mean_ns; /* latency of completed requests;
-                                 percentile q is the sorted sample at rank
-                                 round(q (count - 1)) */
+    double p50_ns, p99_ns, max_ns, mean_ns; /* latency over all classes (as in
+                                 hsma_latency_summary) */
     double solves_per_s;      /* completed / (last completion - first submit) */
     int64_t rounds;           /* admission rounds that launched work */
     double launch_ms;         /* scheduler time spent enqueueing work */
+    double t_first_submit_ns, t_last_done_ns; /* on hsma_clock_ns()'s clock */
+    hsma_latency_summary all; /* the same figures as p50_ns .. mean_ns */
+    hsma_latency_summary by_class[HSMA_LATENCY_CLASSES];
 } hsma_queue_statistics;
 
 typedef struct hsma_queue hsma_queue;
@@ -392,10 +418,18 @@ hsma_status hsma_queue_wait(hsma_queue *queue, uint64_t ticket, int64_t timeout_
 
 /* Forget a finished request and free what the server holds for it (a kept
  * synthetic result).  Still running -> HSMA_PENDING, nothing done.  Records of
- * finished requests stay until released. */
+ * finished requests stay until released (except fire-and-forget requests,
+ * release_on_completion = 2, whose records go when they finish). */
 hsma_status hsma_queue_release(hsma_queue *queue, uint64_t ticket);
 
+/* Counters, budget and latency statistics (a snapshot; the percentiles are
+ * worked out after the queue's lock is released). */
 hsma_status hsma_queue_stats(hsma_queue *queue, hsma_queue_statistics *stats);
+
+/* Start a new latency window: clear the latency statistics; from then on
+ * only requests whose arrival time is >= t_from_ns enter them (a warm-up
+ * period is left out by passing its end).  The counters are not reset. */
+hsma_status hsma_queue_stats_reset(hsma_queue *queue, double t_from_ns);
 
 /* Close the queue: later submits fail with HSMA_QUEUE_CLOSED, everything
  * admissible still runs to completion, requests that can no longer be

@@ -87,6 +87,16 @@ class RequestInfo(ctypes.Structure):
                 ("lda", ctypes.c_int64), ("ldb", ctypes.c_int64)]
 
 
+class LatencySummary(ctypes.Structure):
+    _fields_ = [("count", ctypes.c_int64), ("p50_ns", ctypes.c_double),
+                ("p99_ns", ctypes.c_double), ("max_ns", ctypes.c_double),
+                ("mean_ns", ctypes.c_double)]
+
+
+LATENCY_CLASSES = 3
+LATENCY_CLASS_NAMES = ["m<=64", "64<m<=512", "m>512"]
+
+
 class QueueStatistics(ctypes.Structure):
     _fields_ = [("submitted", ctypes.c_int64), ("rejected", ctypes.c_int64),
                 ("completed", ctypes.c_int64), ("failed", ctypes.c_int64),
@@ -95,7 +105,9 @@ class QueueStatistics(ctypes.Structure):
                 ("p50_ns", ctypes.c_double), ("p99_ns", ctypes.c_double),
                 ("max_ns", ctypes.c_double), ("mean_ns", ctypes.c_double),
                 ("solves_per_s", ctypes.c_double), ("rounds", ctypes.c_int64),
-                ("launch_ms", ctypes.c_double)]
+                ("launch_ms", ctypes.c_double),
+                ("t_first_submit_ns", ctypes.c_double), ("t_last_done_ns", ctypes.c_double),
+                ("all", LatencySummary), ("by_class", LatencySummary * LATENCY_CLASSES)]
 
 
 BACKEND_HIP, BACKEND_SIMULATED = 0, 1
@@ -166,6 +178,8 @@ def lib():
         L.hsma_queue_release.restype = i32
         L.hsma_queue_stats.argtypes = [vp, ctypes.POINTER(QueueStatistics)]
         L.hsma_queue_stats.restype = i32
+        L.hsma_queue_stats_reset.argtypes = [vp, ctypes.c_double]
+        L.hsma_queue_stats_reset.restype = i32
         L.hsma_queue_destroy.argtypes = [vp]
         L.hsma_queue_destroy.restype = i32
         _lib = L
@@ -459,9 +473,12 @@ def clock_ns() -> float:
 
 def request(m: int, n: int, alpha=1.0, unit: bool = False, complex_: bool = False,
             key: Optional[int] = None, L=None, B=None, release_on_completion: bool = True,
-            t_arrival_ns: float = 0.0) -> Request:
+            t_arrival_ns: float = 0.0, forget: bool = False) -> Request:
     """A queue request: synthetic (``key`` given; the server allocates and
-    fills L and B) or on caller tensors ``L``, ``B``."""
+    fills L and B) or on caller tensors ``L``, ``B``.  ``forget`` makes it
+    fire-and-forget (release_on_completion = 2): its record is dropped when it
+    finishes, so poll/wait then report NOT_FOUND; it still counts in the
+    statistics."""
     code = C64F if complex_ else R64F
     a = complex(alpha)
     if code == R64F and a.imag != 0:
@@ -469,10 +486,10 @@ def request(m: int, n: int, alpha=1.0, unit: bool = False, complex_: bool = Fals
     if key is not None:
         prob = Problem(UNIT if unit else NON_UNIT, code, m, n, a.real, a.imag, None, max(1, m),
                        None, max(1, m))
-        return Request(prob, INPUT_SYNTHETIC, 1 if release_on_completion else 0,
+        return Request(prob, INPUT_SYNTHETIC, 2 if forget else (1 if release_on_completion else 0),
                        key & (2**64 - 1), t_arrival_ns)
     prob = problem_struct(L, B, alpha, unit)
-    return Request(prob, INPUT_DEVICE, 0, 0, t_arrival_ns)
+    return Request(prob, INPUT_DEVICE, 2 if forget else 0, 0, t_arrival_ns)
 
 
 def request_footprint(req: Request) -> int:
@@ -539,7 +556,18 @@ class Queue:
     def stats(self) -> dict:
         s = QueueStatistics()
         _check(lib().hsma_queue_stats(self._h, ctypes.byref(s)), "hsma_queue_stats")
-        return {f[0]: getattr(s, f[0]) for f in QueueStatistics._fields_}
+
+        def summ(x):
+            return {f[0]: getattr(x, f[0]) for f in LatencySummary._fields_}
+        out = {f[0]: getattr(s, f[0]) for f in QueueStatistics._fields_
+               if f[0] not in ("all", "by_class")}
+        out["all"] = summ(s.all)
+        out["by_class"] = {LATENCY_CLASS_NAMES[c]: summ(s.by_class[c]) for c in range(LATENCY_CLASSES)}
+        return out
+
+    def stats_reset(self, t_from_ns: float) -> None:
+        """New latency window: only arrivals at or after ``t_from_ns`` count."""
+        _check(lib().hsma_queue_stats_reset(self._h, t_from_ns), "hsma_queue_stats_reset")
 
     def close(self) -> None:
         if self._h:

@@ -19,14 +19,14 @@ hsma_status blocked_trsm(bool cx, bool unit, int64_t m, int64_t n, cplx alpha, c
 hsma_status blocked_trsm_graph(bool cx, bool unit, int64_t m, int64_t n, cplx alpha,
                                const double *A, int64_t lda, double *B, int64_t ldb, int ib,
                                bool mixed, hipStream_t s);
-hsma_status blocked_residual(bool cx, bool unit, int64_t m, int64_t n, const double *A, int64_t lda,
-                             const double *X, int64_t ldx, double *R, int64_t ldr, int ib,
-                             hipStream_t s);
-hsma_status launch_scale_copy(const double *S, int64_t lds, double *D, int64_t ldd, int64_t m,
-                              int64_t n, double alpha, hipStream_t s);
-hsma_status launch_axpy(const double *S, int64_t lds, double *D, int64_t ldd, int64_t m, int64_t n,
-                        hipStream_t s);
-hsma_status launch_rowsum_abs(const double *M, int64_t ld, int64_t m, int64_t n, int tri,
+hsma_status triangular_residual(bool cx, bool unit, int64_t m, int64_t n, const double *A,
+                                int64_t lda, const double *X, int64_t ldx, double *R, int64_t ldr,
+                                hipStream_t s);
+hsma_status launch_scale_copy(bool cx, const double *S, int64_t lds, double *D, int64_t ldd,
+                              int64_t m, int64_t n, cplx alpha, hipStream_t s);
+hsma_status launch_axpy(bool cx, const double *S, int64_t lds, double *D, int64_t ldd, int64_t m,
+                        int64_t n, hipStream_t s);
+hsma_status launch_rowsum_abs(bool cx, const double *M, int64_t ld, int64_t m, int64_t n, int tri,
                               double *out, double *partial, hipStream_t s);
 int64_t rowsum_slabs(int64_t n);
 
@@ -148,16 +148,17 @@ static hsma_status solve_once(bool cx, bool unit, int64_t m, int64_t n, cplx al,
     return st != HSMA_SUCCESS ? st : st2;
 }
 
-// Normwise backward error from the residual R (real data, on the device):
-// max row sums of |R|, tril(L), X and B0, combined on the host.
-static hsma_status backward_error_host(bool unit, int64_t m, int64_t n, double alpha,
+// Normwise backward error from the residual R (on the device): max row sums
+// of |R|, tril(L), X and B0 (complex modulus for complex data), combined on
+// the host.
+static hsma_status backward_error_host(bool cx, bool unit, int64_t m, int64_t n, cplx alpha,
                                        const double *Ad, int64_t lda, const double *X,
                                        int64_t ldx, const double *B0, int64_t ldb0,
                                        const double *R, int64_t ldr, double *sums, double *partial,
                                        double *lnorm, double *eta, hipStream_t s) {
     std::vector<double> h(3 * m);
     if (*lnorm < 0) {
-        HSMA_TRY(launch_rowsum_abs(Ad, lda, m, m, unit ? 2 : 1, sums, partial, s));
+        HSMA_TRY(launch_rowsum_abs(cx, Ad, lda, m, m, unit ? 2 : 1, sums, partial, s));
         std::vector<double> hl(m);
         HSMA_HIP(hipMemcpyAsync(hl.data(), sums, m * sizeof(double), hipMemcpyDeviceToHost, s));
         HSMA_HIP(hipStreamSynchronize(s));
@@ -165,9 +166,9 @@ static hsma_status backward_error_host(bool unit, int64_t m, int64_t n, double a
         for (double v : hl) mx = (v > mx || std::isnan(v)) ? v : mx;
         *lnorm = mx;
     }
-    HSMA_TRY(launch_rowsum_abs(R, ldr, m, n, 0, sums, partial, s));
-    HSMA_TRY(launch_rowsum_abs(X, ldx, m, n, 0, sums + m, partial, s));
-    HSMA_TRY(launch_rowsum_abs(B0, ldb0, m, n, 0, sums + 2 * m, partial, s));
+    HSMA_TRY(launch_rowsum_abs(cx, R, ldr, m, n, 0, sums, partial, s));
+    HSMA_TRY(launch_rowsum_abs(cx, X, ldx, m, n, 0, sums + m, partial, s));
+    HSMA_TRY(launch_rowsum_abs(cx, B0, ldb0, m, n, 0, sums + 2 * m, partial, s));
     HSMA_HIP(hipMemcpyAsync(h.data(), sums, 3 * m * sizeof(double), hipMemcpyDeviceToHost, s));
     HSMA_HIP(hipStreamSynchronize(s));
     double r = 0, x = 0, b = 0;
@@ -176,7 +177,7 @@ static hsma_status backward_error_host(bool unit, int64_t m, int64_t n, double a
         x = (h[m + i] > x || std::isnan(h[m + i])) ? h[m + i] : x;
         b = (h[2 * m + i] > b || std::isnan(h[2 * m + i])) ? h[2 * m + i] : b;
     }
-    const double den = *lnorm * x + std::fabs(alpha) * b;
+    const double den = *lnorm * x + std::hypot(alpha.re, alpha.im) * b;
     *eta = den > 0 ? r / den : r;
     return HSMA_SUCCESS;
 }
@@ -194,7 +195,6 @@ hsma_status trsm_impl(hsma_diag diag, int64_t m, int64_t n, const void *alpha, c
     const int steps = opt ? opt->refine_steps : 0;
     const bool want_eta = opt && (opt->want_backward_error || opt->refine_steps < 0);
     if (mixed && cx) return HSMA_NOT_SUPPORTED;
-    if ((steps != 0 || want_eta) && cx) return HSMA_NOT_SUPPORTED;
     if (quick) {
         if (rep) rep->backward_error = want_eta ? 0.0 : -1.0;
         return HSMA_SUCCESS;
@@ -212,11 +212,12 @@ hsma_status trsm_impl(hsma_diag diag, int64_t m, int64_t n, const void *alpha, c
         return solve_once(cx, unit, m, n, al, Ad, lda, Bd, ldb, ib_override, path, mixed, s,
                           path_used, ib_used, opt && opt->use_graph == 1);
 
-    // Refinement / backward error (real data): keep B0, then iterate.
+    // Refinement / backward error: keep B0, then iterate.
+    const int es = cx ? 2 : 1;
     const double tol = (opt && opt->refine_tol > 0) ? opt->refine_tol : 1e-13;
     const int max_steps = steps < 0 ? 4 : steps;
     void *ws = nullptr;
-    const size_t mn = (size_t)m * n;
+    const size_t mn = (size_t)m * n * es;
     const size_t slabs = (size_t)std::max<int64_t>(rowsum_slabs(n), rowsum_slabs(m));
     HSMA_TRY(ws_alloc(&ws, (2 * mn + (3 + slabs) * (size_t)m) * sizeof(double), s));
     double *B0 = static_cast<double *>(ws);
@@ -226,32 +227,31 @@ hsma_status trsm_impl(hsma_diag diag, int64_t m, int64_t n, const void *alpha, c
     hsma_status st = HSMA_SUCCESS;
     int used = 0;
     double eta = -1.0, lnorm = -1.0;
-    int ibr = ib_override > 0 ? ib_override : lookup_block_size(false, m, n);
-    if (!valid_block_size(false, ibr)) ibr = 128;
-    if (hipMemcpy2DAsync(B0, m * sizeof(double), Bd, ldb * sizeof(double), m * sizeof(double), n,
-                         hipMemcpyDeviceToDevice, s) != hipSuccess)
+    const size_t col = (size_t)es * sizeof(double);
+    if (hipMemcpy2DAsync(B0, m * col, Bd, ldb * col, m * col, n, hipMemcpyDeviceToDevice, s) !=
+        hipSuccess)
         st = hip_fail(hipGetLastError());
     if (st == HSMA_SUCCESS)
-        st = solve_once(false, unit, m, n, al, Ad, lda, Bd, ldb, ib_override, path, mixed, s,
+        st = solve_once(cx, unit, m, n, al, Ad, lda, Bd, ldb, ib_override, path, mixed, s,
                         path_used, ib_used);
     while (st == HSMA_SUCCESS) {
         const bool more = used < max_steps;
         if (!more && !want_eta) break;
         // R = alpha B0 - L X
-        st = launch_scale_copy(B0, m, R, m, m, n, al.re, s);
-        if (st == HSMA_SUCCESS) st = blocked_residual(false, unit, m, n, Ad, lda, Bd, ldb, R, m, ibr, s);
+        st = launch_scale_copy(cx, B0, m, R, m, m, n, al, s);
+        if (st == HSMA_SUCCESS) st = triangular_residual(cx, unit, m, n, Ad, lda, Bd, ldb, R, m, s);
         if (st != HSMA_SUCCESS) break;
         if (want_eta) {
-            st = backward_error_host(unit, m, n, al.re, Ad, lda, Bd, ldb, B0, m, R, m, sums, partial,
-                                     &lnorm, &eta, s);
+            st = backward_error_host(cx, unit, m, n, al, Ad, lda, Bd, ldb, B0, m, R, m, sums,
+                                     partial, &lnorm, &eta, s);
             if (st != HSMA_SUCCESS) break;
             if (steps < 0 && eta <= tol) break;
         }
         if (!more) break;
         // L D = R, X += D
-        st = solve_once(false, unit, m, n, cplx{1.0, 0.0}, Ad, lda, R, m, ib_override, path, mixed,
-                        s, nullptr, nullptr);
-        if (st == HSMA_SUCCESS) st = launch_axpy(R, m, Bd, ldb, m, n, s);
+        st = solve_once(cx, unit, m, n, cplx{1.0, 0.0}, Ad, lda, R, m, ib_override, path, mixed, s,
+                        nullptr, nullptr);
+        if (st == HSMA_SUCCESS) st = launch_axpy(cx, R, m, Bd, ldb, m, n, s);
         if (st == HSMA_SUCCESS) ++used;
         if (!want_eta && used >= max_steps) break;
     }

@@ -173,51 +173,22 @@ hsma_status blocked_trsm(bool cx, bool unit, int64_t m, int64_t n, cplx alpha, c
     return recurse(c, 0, nblk, false);
 }
 
-// R <- R - tril(L) X for the iterative-refinement residual (FP64 products):
-// the same recursion as the solve, with triangle-masked products on the
-// diagonal blocks (only the lower triangle of each block is read; a unit
-// diagonal is taken as 1).
-namespace {
-struct RCtx {
-    bool cx, unit;
-    int64_t m, n;
-    const double *A;
-    int64_t lda;
-    const double *X;
-    int64_t ldx;
-    double *R;
-    int64_t ldr;
-    int ib;
-    hipStream_t s;
-};
-
-hsma_status residual_rec(const RCtx &c, int64_t b0, int64_t nb) {
-    const int es = c.cx ? 2 : 1;
+// R <- R - tril(L) X, the residual of refinement and of the backward-error
+// report (FP64 products).  One product over the whole triangle: each row
+// tile accumulates its full row of L times X in one FP64 accumulator chain
+// (K up to the tile's last row, the part above the diagonal masked to zero,
+// a unit diagonal taken as 1) and subtracts it from R once.  This order has
+// nothing in common with the solve's recursion, so the rounding of the solve's
+// updates does not cancel out of the residual and the reported backward error
+// measures the solve, not its leaves alone.
+hsma_status triangular_residual(bool cx, bool unit, int64_t m, int64_t n, const double *A,
+                                int64_t lda, const double *X, int64_t ldx, double *R, int64_t ldr,
+                                hipStream_t s) {
+    const int es = cx ? 2 : 1;
     GemmBatch one;
-    if (nb == 1) {
-        const int64_t r0 = b0 * c.ib;
-        const int mr = (int)std::min<int64_t>(c.ib, c.m - r0);
-        return launch_gemm(c.cx, GemmRole::Residual, es * mr, (int)c.n, es * mr, cplx{-1.0, 0.0},
-                           c.A + es * (r0 + r0 * c.lda), c.lda, c.X + es * r0, es * c.ldx,
-                           cplx{1.0, 0.0}, c.R + es * r0, es * c.ldr, c.unit ? 2 : 1, one, c.s);
-    }
-    const int64_t h = nb / 2;
-    HSMA_TRY(residual_rec(c, b0, h));
-    const int64_t r1 = (b0 + h) * c.ib, r2 = std::min<int64_t>((b0 + nb) * c.ib, c.m);
-    const int64_t k0 = b0 * c.ib;
-    HSMA_TRY(launch_gemm(c.cx, GemmRole::Residual, (int)(es * (r2 - r1)), (int)c.n,
-                         (int)(es * (r1 - k0)), cplx{-1.0, 0.0}, c.A + es * (r1 + k0 * c.lda), c.lda,
-                         c.X + es * k0, es * c.ldx, cplx{1.0, 0.0}, c.R + es * r1, es * c.ldr, 0, one,
-                         c.s));
-    return residual_rec(c, b0 + h, nb - h);
-}
-}  // namespace
-
-hsma_status blocked_residual(bool cx, bool unit, int64_t m, int64_t n, const double *A, int64_t lda,
-                             const double *X, int64_t ldx, double *R, int64_t ldr, int ib,
-                             hipStream_t s) {
-    RCtx c{cx, unit, m, n, A, lda, X, ldx, R, ldr, ib, s};
-    return residual_rec(c, 0, (m + ib - 1) / ib);
+    return launch_gemm(cx, GemmRole::Residual, (int)(es * m), (int)n, (int)(es * m),
+                       cplx{-1.0, 0.0}, A, lda, X, es * ldx, cplx{1.0, 0.0}, R, es * ldr,
+                       unit ? 2 : 1, one, s, /*k_lower=*/1);
 }
 
 }  // namespace hsma

@@ -93,7 +93,10 @@ __device__ __forceinline__ void gemm_tile(const GemmParams &p, const GD *__restr
     __shared__ double Bs[2][BN * LDB_S];
 
     const int m0 = tm * BM, n0 = tn * BN;
-    const int M = p.M, N = p.N, K = p.K;
+    const int M = p.M, N = p.N;
+    // A lower-triangular A (k_lower) has nothing right of column m0 + BM - 1
+    // in this tile's rows.
+    const int K = (p.k_lower && m0 + BM < p.K) ? m0 + BM : p.K;
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     const int wm0 = (wave % WM) * TM, wn0 = (wave / WM) * TN;
@@ -648,7 +651,7 @@ hsma_status launch_gemm_grouped(bool cplx_, GemmRole role, int bm, int bn, const
 hsma_status launch_gemm(bool cplx_, GemmRole role, int M, int N, int K, cplx alpha,
                         const double *A, int64_t lda, const double *B, int64_t ldb, cplx beta,
                         double *C, int64_t ldc, int tri_a, const GemmBatch &batch,
-                        hipStream_t s) {
+                        hipStream_t s, int k_lower) {
     if (M <= 0 || N <= 0 || batch.count <= 0) return HSMA_SUCCESS;
     GemmParams p{};
     p.M = M;
@@ -665,6 +668,7 @@ hsma_status launch_gemm(bool cplx_, GemmRole role, int M, int N, int K, cplx alp
     p.beta_re = beta.re;
     p.beta_im = beta.im;
     p.tri_a = tri_a;
+    p.k_lower = (k_lower && tri_a) ? 1 : 0;
     p.inner = batch.inner > 0 ? batch.inner : 1;
     p.a_outer = batch.a_outer;
     p.a_inner = batch.a_inner;

@@ -44,7 +44,9 @@ constexpr size_t kMaxEntries = 32;
 std::mutex g_mu;
 std::list<Entry> g_lru;        // front = most recently used
 hipStream_t g_capture[64] = {};
-bool g_capturing = false;
+// Per thread: captures use hipStreamCaptureModeThreadLocal, so only the
+// capturing thread's own calls are recorded and must see the flag.
+thread_local bool g_capturing = false;
 
 void destroy(Entry &e) {
     if (e.exec) (void)hipGraphExecDestroy(e.exec);

@@ -109,6 +109,8 @@ struct GemmParams {
     int64_t a_outer, a_inner, b_outer, b_inner, c_outer, c_inner;
     int tiles_m, tiles_n;
     int tile0;            // grouped launch: first tile of this product in the grid
+    int k_lower;          // 1: A is lower triangular as a whole (with tri_a), so a
+                          // tile of rows [m0, m0 + BM) stops its K loop at m0 + BM
 };
 
 // Tile shape a grouped launch of `role` uses when its largest product has
@@ -125,10 +127,12 @@ struct GemmBatch {
     int count = 1, inner = 1;
     int64_t a_outer = 0, a_inner = 0, b_outer = 0, b_inner = 0, c_outer = 0, c_inner = 0;
 };
+// k_lower = 1: A (with tri_a != 0) is a whole lower-triangular matrix, so
+// each row tile reads only the columns left of its last row.
 hsma_status launch_gemm(bool cplx_, GemmRole role, int M, int N, int K,
                         cplx alpha, const double *A, int64_t lda, const double *B,
                         int64_t ldb, cplx beta, double *C, int64_t ldc, int tri_a,
-                        const GemmBatch &batch, hipStream_t s);
+                        const GemmBatch &batch, hipStream_t s, int k_lower = 0);
 
 // Inverse of every diagonal sub-block of edge `base` (<= 64) along the
 // diagonal of L (m rows, partitioned into consecutive chunks of `base`, last

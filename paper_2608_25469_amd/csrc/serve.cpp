@@ -22,7 +22,9 @@
 // modelled completion times so the scheduler can be tested without a GPU.
 
 #include <algorithm>
+#include <array>
 #include <chrono>
+#include <cmath>
 #include <condition_variable>
 #include <cstring>
 #include <deque>
@@ -97,6 +99,56 @@ struct Inflight {
     std::vector<Req *> reqs;
 };
 
+// Latency histogram: bin 0 holds samples below kLo; bin b >= 1 holds
+// [kLo 2^((b-1)/kSub), kLo 2^(b/kSub)); the last bin also takes everything
+// above its lower edge.  Fixed size, so recording and summarising cost the
+// same however long the queue runs.
+struct LatHist {
+    static constexpr int kSub = 64;        // bins per doubling
+    static constexpr double kLo = 1e3;     // 1 us
+    static constexpr int kBins = 64 * 32;  // up to about 4.3e12 ns
+    std::array<int64_t, kBins + 1> n{};
+    int64_t count = 0;
+    double sum = 0, min = 0, max = 0;
+
+    void add(double x) {
+        int b = 0;
+        if (x >= kLo) {
+            b = 1 + (int)std::floor(std::log2(x / kLo) * kSub);
+            b = std::min(std::max(b, 1), kBins);
+        }
+        n[b]++;
+        if (count == 0 || x < min) min = x;
+        if (count == 0 || x > max) max = x;
+        count++;
+        sum += x;
+    }
+    // Sample of rank round(q (count - 1)) as its bin's geometric midpoint,
+    // clamped to the observed range.
+    double quantile(double q) const {
+        if (count == 0) return 0.0;
+        const int64_t rank = (int64_t)(q * (double)(count - 1) + 0.5);
+        int64_t c = 0;
+        int b = 0;
+        for (; b <= kBins; ++b) {
+            c += n[b];
+            if (c > rank) break;
+        }
+        double v = b == 0 ? min : kLo * std::exp2(((double)b - 0.5) / kSub);
+        return std::min(std::max(v, min), max);
+    }
+    void summary(hsma_latency_summary *o) const {
+        o->count = count;
+        o->p50_ns = quantile(0.50);
+        o->p99_ns = quantile(0.99);
+        o->max_ns = count ? max : 0.0;
+        o->mean_ns = count ? sum / (double)count : 0.0;
+    }
+};
+
+// Latency class of a request: m <= 64, 64 < m <= 512, m > 512.
+int latency_class(int64_t m) { return m <= 64 ? 0 : (m <= 512 ? 1 : 2); }
+
 }  // namespace
 }  // namespace hsma
 
@@ -119,8 +171,9 @@ struct hsma_queue {
     std::vector<double> sim_free_at;  // simulation: per-stream busy-until (last = small)
     // Device frees decided under the lock, issued after it is released.
     std::vector<std::pair<void *, hipStream_t>> deferred;
-    // statistics
-    std::vector<double> latencies_ns;
+    // statistics: [0] every class, [1 + c] latency class c
+    hsma::LatHist lat[1 + HSMA_LATENCY_CLASSES];
+    double stats_from_ns = -1e300;  // latency window: arrivals at or after this
     int64_t submitted = 0, rejected = 0, completed = 0, failed = 0, rounds = 0;
     double t_first_submit = 0, t_last_done = 0, launch_ns = 0;
 };
@@ -154,7 +207,8 @@ void free_deferred(hsma_queue *q, std::unique_lock<std::mutex> &lk) {
     lk.lock();
 }
 
-// Called with the lock held.
+// Called with the lock held.  A fire-and-forget request (release_on_completion
+// = 2) is deleted here: the caller must not touch r afterwards.
 void finish(hsma_queue *q, Req *r, double t, hsma_status st) {
     r->t_done = t;
     r->state = st == HSMA_SUCCESS ? DONE : FAILED;
@@ -162,17 +216,25 @@ void finish(hsma_queue *q, Req *r, double t, hsma_status st) {
     q->n_inflight--;
     if (st == HSMA_SUCCESS) {
         q->completed++;
-        q->latencies_ns.push_back(t - r->t_arrival);
+        if (r->t_arrival >= q->stats_from_ns) {
+            const double lat = t - r->t_arrival;
+            q->lat[0].add(lat);
+            q->lat[1 + latency_class(r->r.prob.m)].add(lat);
+        }
     } else {
         q->failed++;
     }
     q->t_last_done = std::max(q->t_last_done, t);
     const bool keep = st == HSMA_SUCCESS && r->r.input == HSMA_INPUT_SYNTHETIC &&
-                      !r->r.release_on_completion;
+                      r->r.release_on_completion == 0;
     const size_t keep_bytes = keep ? data_bytes(r->r.prob) : 0;
     if (!keep) release_mem(q, r);
     q->budget_used -= r->held - keep_bytes;
     r->held = keep_bytes;
+    if (r->r.release_on_completion == 2) {
+        q->all.erase(r->ticket);
+        delete r;
+    }
 }
 
 // Size classes of one admission round: m <= 64, then 64 < m <= 512 and
@@ -197,7 +259,7 @@ void launch_admitted(hsma_queue *q, std::vector<Req *> &adm) {
         // One allocation for the class's auto-released synthetic inputs.
         size_t shared_bytes = 0;
         for (Req *r : cls[c])
-            if (r->r.input == HSMA_INPUT_SYNTHETIC && r->r.release_on_completion)
+            if (r->r.input == HSMA_INPUT_SYNTHETIC && r->r.release_on_completion != 0)
                 shared_bytes += (data_bytes(r->r.prob) + 255) / 256 * 256;
         Block *blk = nullptr;
         hsma_status blk_st = HSMA_SUCCESS;
@@ -216,7 +278,7 @@ void launch_admitted(hsma_queue *q, std::vector<Req *> &adm) {
             if (r->r.input == HSMA_INPUT_SYNTHETIC) {
                 unsigned char *mem = nullptr;
                 hsma_status st = HSMA_SUCCESS;
-                if (r->r.release_on_completion) {
+                if (r->r.release_on_completion != 0) {
                     st = blk_st;
                     if (st == HSMA_SUCCESS) {
                         mem = static_cast<unsigned char *>(blk->mem) + blk_off;
@@ -436,9 +498,10 @@ hsma_status hsma_queue_create(const hsma_queue_config *cfg, hsma_queue **out) {
         return HSMA_INVALID_VALUE;
     if (c.max_inflight < 0 || c.n_streams < 0 || c.poll_us < 0 || c.sim_fixed_ns < 0)
         return HSMA_INVALID_VALUE;
-    // A third of the device's 288 GB: at 40 000 requests/s a 32 GiB budget
-    // held admission back (p50 290 ms) where 96 GiB kept up (p50 63 ms).
-    if (c.hbm_budget_bytes == 0) c.hbm_budget_bytes = (uint64_t)96 << 30;
+    // 32 GiB by default; larger budgets (a third of the 288 GB, say) are for
+    // offered loads well above 20 000 requests/s, where 32 GiB holds
+    // admission back.
+    if (c.hbm_budget_bytes == 0) c.hbm_budget_bytes = (uint64_t)32 << 30;
     if (c.max_inflight == 0) c.max_inflight = 8192;
     // Eight streams: an admission round has up to four blocked classes, and
     // rounds overlap (at 20 000 requests/s p50 fell from 27 to 23 ms going
@@ -481,7 +544,7 @@ hsma_status hsma_queue_submit(hsma_queue *q, const hsma_request *reqs, int64_t c
         const hsma_problem &p = r.prob;
         if (r.input != HSMA_INPUT_DEVICE && r.input != HSMA_INPUT_SYNTHETIC)
             return HSMA_INVALID_VALUE;
-        if (r.release_on_completion != 0 && r.release_on_completion != 1)
+        if (r.release_on_completion < 0 || r.release_on_completion > 2)
             return HSMA_INVALID_VALUE;
         const bool syn = r.input == HSMA_INPUT_SYNTHETIC;
         const double al[2] = {p.alpha_re, p.alpha_im};
@@ -545,8 +608,13 @@ hsma_status hsma_queue_wait(hsma_queue *q, uint64_t ticket, int64_t timeout_ns,
         }
         if (q->stopped) return HSMA_QUEUE_CLOSED;
         if (q->cv_done.wait_until(lk, deadline) == std::cv_status::timeout) {
-            hsma::fill_info(r, info);
-            return HSMA_TIMEOUT;
+            // Look the ticket up again: a fire-and-forget request may have
+            // finished and been dropped while the lock was released.
+            auto again = q->all.find(ticket);
+            if (again == q->all.end()) return HSMA_NOT_FOUND;
+            hsma::fill_info(again->second, info);
+            return hsma::state_status(again->second) == HSMA_PENDING ? HSMA_TIMEOUT
+                                                                     : hsma::state_status(again->second);
         }
     }
 }
@@ -574,31 +642,41 @@ hsma_status hsma_queue_release(hsma_queue *q, uint64_t ticket) {
 
 hsma_status hsma_queue_stats(hsma_queue *q, hsma_queue_statistics *st) {
     if (!q || !st) return HSMA_INVALID_POINTER;
-    std::lock_guard<std::mutex> lk(q->mu);
     std::memset(st, 0, sizeof(*st));
-    st->submitted = q->submitted;
-    st->rejected = q->rejected;
-    st->completed = q->completed;
-    st->failed = q->failed;
-    st->pending = (int64_t)q->pending.size();
-    st->inflight = q->n_inflight;
-    st->bytes_in_use = q->budget_used;
-    st->bytes_peak = q->budget_peak;
-    st->rounds = q->rounds;
-    st->launch_ms = q->launch_ns * 1e-6;
-    if (!q->latencies_ns.empty()) {
-        std::vector<double> v = q->latencies_ns;
-        std::sort(v.begin(), v.end());
-        auto pct = [&](double p) { return v[(size_t)(p * (double)(v.size() - 1) + 0.5)]; };
-        st->p50_ns = pct(0.50);
-        st->p99_ns = pct(0.99);
-        st->max_ns = v.back();
-        double sum = 0;
-        for (double x : v) sum += x;
-        st->mean_ns = sum / (double)v.size();
-        const double span = q->t_last_done - q->t_first_submit;
-        st->solves_per_s = span > 0 ? (double)q->completed / (span * 1e-9) : 0.0;
+    // Copy under the lock (a fixed-size histogram), summarise after it.
+    std::vector<hsma::LatHist> lat(1 + HSMA_LATENCY_CLASSES);
+    {
+        std::lock_guard<std::mutex> lk(q->mu);
+        st->submitted = q->submitted;
+        st->rejected = q->rejected;
+        st->completed = q->completed;
+        st->failed = q->failed;
+        st->pending = (int64_t)q->pending.size();
+        st->inflight = q->n_inflight;
+        st->bytes_in_use = q->budget_used;
+        st->bytes_peak = q->budget_peak;
+        st->rounds = q->rounds;
+        st->launch_ms = q->launch_ns * 1e-6;
+        st->t_first_submit_ns = q->t_first_submit;
+        st->t_last_done_ns = q->t_last_done;
+        for (int c = 0; c <= HSMA_LATENCY_CLASSES; ++c) lat[c] = q->lat[c];
     }
+    lat[0].summary(&st->all);
+    for (int c = 0; c < HSMA_LATENCY_CLASSES; ++c) lat[1 + c].summary(&st->by_class[c]);
+    st->p50_ns = st->all.p50_ns;
+    st->p99_ns = st->all.p99_ns;
+    st->max_ns = st->all.max_ns;
+    st->mean_ns = st->all.mean_ns;
+    const double span = st->t_last_done_ns - st->t_first_submit_ns;
+    st->solves_per_s = (st->completed > 0 && span > 0) ? (double)st->completed / (span * 1e-9) : 0.0;
+    return HSMA_SUCCESS;
+}
+
+hsma_status hsma_queue_stats_reset(hsma_queue *q, double t_from_ns) {
+    if (!q) return HSMA_INVALID_POINTER;
+    std::lock_guard<std::mutex> lk(q->mu);
+    for (auto &h : q->lat) h = hsma::LatHist();
+    q->stats_from_ns = t_from_ns;
     return HSMA_SUCCESS;
 }
 

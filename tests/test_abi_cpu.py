@@ -138,6 +138,7 @@ STRUCTS = {
     "hsma_request": hs.Request,
     "hsma_request_info": hs.RequestInfo,
     "hsma_queue_statistics": hs.QueueStatistics,
+    "hsma_latency_summary": hs.LatencySummary,
 }
 
 

@@ -5,6 +5,7 @@ import pytest
 
 import oracle
 import workloads as W
+from parity import assert_parity
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -58,9 +59,7 @@ def test_batched_matches_oracle_and_single_calls():
         X = hs.from_colmajor(Bd)
         Xs = hs.from_colmajor(Bs)
         assert X.tobytes() == Xs.tobytes(), "batched differs from single call"
-        ref = oracle.solve(L, B, a, unit=u)
-        assert oracle.rel_err_fro(X, ref) <= 1e-12
-        assert oracle.backward_error(L, X, B, a, unit=u) <= 10 * B.shape[0] * U
+        assert_parity(L, B, X, a, unit=u, tag=("batched", B.shape))
 
 
 def test_batched_workload_subset():
@@ -69,14 +68,9 @@ def test_batched_workload_subset():
     pl, pb, vl, vb = hs.pack_batch(b.L, b.B)
     hs.trsm_batched([(L, B, b.alpha, False) for L, B in zip(vl, vb)])
     torch.cuda.synchronize()
-    worst = 0.0
     for i in range(0, 2000, 7):
         X = hs.from_colmajor(vb[i])
-        ref = oracle.solve(b.L[i], b.B[i], b.alpha)
-        rel = oracle.rel_err_fro(X, ref)
-        eta = oracle.backward_error(b.L[i], X, b.B[i], b.alpha)
-        worst = max(worst, rel)
-        assert rel <= 1e-12 and eta <= 10 * b.shapes[i][0] * U, (i, b.shapes[i], rel, eta)
+        assert_parity(b.L[i], b.B[i], X, b.alpha, tag=(i, b.shapes[i]))
 
 
 def test_plan_repeats_bitwise():

@@ -9,6 +9,7 @@ import pytest
 
 import oracle
 import workloads as W
+from parity import assert_parity
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -44,14 +45,10 @@ def run(L, B, alpha, unit=False, block_size=0, path=0, ldb=None, lda=None):
 
 
 def check(L, B, X, alpha, unit=False, tag=""):
-    ref = oracle.solve(L, B, alpha, unit=unit)
-    rel = oracle.rel_err_fro(X, ref)
-    eta = oracle.backward_error(L, X, B, alpha, unit=unit)
-    m = B.shape[0]
-    assert np.all(np.isfinite(X)), tag
-    assert rel <= 1e-12, (tag, rel)
-    assert eta <= 10 * m * U, (tag, eta)
-    return rel, eta
+    """Frobenius, per-column and element-wise error against the oracle, and
+    the oracle's backward error of X (see tests/parity.py)."""
+    fro, _, _, eta = assert_parity(L, B, X, alpha, unit=unit, tag=tag)
+    return fro, eta
 
 
 # ---------------------------------------------------------------------------
