@@ -65,7 +65,8 @@ typedef enum {
     HSMA_QUEUE_CLOSED = 8,
     HSMA_PENDING = 9,
     HSMA_TIMEOUT = 10,
-    HSMA_NOT_FOUND = 11
+    HSMA_NOT_FOUND = 11,
+    HSMA_WORKSPACE_TOO_SMALL = 12
 } hsma_status;
 
 /* A hipStream_t, passed as an opaque pointer; NULL = the null stream. */
@@ -102,6 +103,29 @@ hsma_status hsma_trsm(hsma_diag diag, int64_t m, int64_t n, const void *alpha,
                       const void *A, int64_t lda, void *B, int64_t ldb,
                       hsma_dtype dtype, hsma_stream_t stream);
 
+
+/*
+ * hsma_trsm_noalloc -- hsma_trsm for callers that cannot allocate device
+ * memory: code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc.  Same operation, arguments, path choice, I_B and kernels
+ * as hsma_trsm, so the result is bit-for-bit the same; it calls no hipMalloc,
+ * hipFree or other allocating routine.  The blocked path's workspace comes
+ * from a fixed per-device scratch array of hsma_noalloc_scratch_bytes()
+ * bytes (64 MiB) inside the library, which each GPU the library runs on
+ * holds until the process ends.  A problem whose workspace does not fit
+ * (hsma_trsm's blocked workspace: ceil(m/I_B) I_B^2 + (ceil(m/2) + I_B) I_B
+ * elements; DTRSM up to m of about 16384 fits) returns
+ * HSMA_WORKSPACE_TOO_SMALL before anything is enqueued.  Every call on one
+ * GPU uses the same array: calls that overlap in time on one GPU (two
+ * streams, two threads) race and give wrong results; serialise them.
+ * Asynchronous on `stream`.
+ */
+hsma_status hsma_trsm_noalloc(hsma_diag diag, int64_t m, int64_t n, const void *alpha,
+                              const void *A, int64_t lda, void *B, int64_t ldb,
+                              hsma_dtype dtype, hsma_stream_t stream);
+
+/* Bytes of the per-device scratch array of hsma_trsm_noalloc. */
+uint64_t hsma_noalloc_scratch_bytes(void);
 
 /* Precision of the blocked path's trailing updates. */
 typedef enum {

@@ -29,6 +29,7 @@ STATUS = {
     0: "SUCCESS", 1: "INVALID_VALUE", 2: "INVALID_SIZE", 3: "INVALID_POINTER",
     4: "ALLOC_FAILED", 5: "HIP_ERROR", 6: "NOT_SUPPORTED", 7: "TOO_LARGE",
     8: "QUEUE_CLOSED", 9: "PENDING", 10: "TIMEOUT", 11: "NOT_FOUND",
+    12: "WORKSPACE_TOO_SMALL",
 }
 
 
@@ -134,6 +135,10 @@ def lib():
         L.hsma_trsm_ex.argtypes = [i32, i64, i64, vp, vp, i64, vp, i64, i32,
                                    ctypes.POINTER(TrsmOptions), ctypes.POINTER(TrsmReport), vp]
         L.hsma_trsm_ex.restype = i32
+        L.hsma_trsm_noalloc.argtypes = [i32, i64, i64, vp, vp, i64, vp, i64, i32, vp]
+        L.hsma_trsm_noalloc.restype = i32
+        L.hsma_noalloc_scratch_bytes.argtypes = []
+        L.hsma_noalloc_scratch_bytes.restype = ctypes.c_uint64
         L.hsma_status_string.argtypes = [i32]
         L.hsma_status_string.restype = ctypes.c_char_p
         L.hsma_last_hip_error.argtypes = []

@@ -281,6 +281,7 @@ const char *hsma_status_string(hsma_status s) {
         case HSMA_PENDING: return "pending";
         case HSMA_TIMEOUT: return "timed out";
         case HSMA_NOT_FOUND: return "not found";
+        case HSMA_WORKSPACE_TOO_SMALL: return "problem needs more workspace than the fixed scratch array holds";
     }
     return "unknown status";
 }

@@ -8,6 +8,9 @@
 
 #include "../../include/hsma.h"
 
+// Size of the allocation-free entry point's per-device scratch array.
+#define HSMA_NOALLOC_SCRATCH_BYTES (64ull << 20)
+
 namespace hsma {
 
 // Record a failing HIP call for hsma_last_hip_error() and turn it into a status.

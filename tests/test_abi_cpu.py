@@ -181,3 +181,25 @@ def test_generate_inputs_validation(lib):
     assert g(0, 0, 4, 1, None, None, None) == 0
     assert g(0, 4, 4, 1, None, ctypes.c_void_p(32), None) == 3
     assert g(1, 4, 4, 1, ctypes.c_void_p(16), None, None) == 3
+
+
+def test_noalloc_rejects_oversized_workspace_before_device(lib):
+    """hsma_trsm_noalloc validates like hsma_trsm and refuses a blocked
+    problem whose workspace exceeds its fixed scratch array before any device
+    call (fake pointers are never dereferenced)."""
+    f = lib.hsma_trsm_noalloc
+    f.argtypes = [ctypes.c_int32, ctypes.c_int64, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
+                  ctypes.c_int64, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p]
+    f.restype = ctypes.c_int32
+    lib.hsma_noalloc_scratch_bytes.restype = ctypes.c_uint64
+    assert lib.hsma_noalloc_scratch_bytes() == 64 << 20
+    one = (ctypes.c_double * 2)(1.0, 0.0)
+    fake = ctypes.c_void_p(0x1000)
+    assert f(0, 40000, 1, one, fake, 40000, fake, 40000, 0, None) == 12
+    assert f(0, 30000, 1, one, fake, 30000, fake, 30000, 1, None) == 12
+    # the documented validation order comes first
+    assert f(2, 40000, 1, one, fake, 40000, fake, 40000, 0, None) == 1
+    assert f(0, 5, 1, one, fake, 4, fake, 5, 0, None) == 2
+    assert f(0, 0, 1, one, None, 1, None, 1, 0, None) == 0
+    assert f(0, 5, 1, None, fake, 5, fake, 5, 0, None) == 3
+    assert lib.hsma_status_string(12)
