@@ -1,4 +1,5 @@
-"""CPU oracle for left-side, lower-triangular, no-transpose TRSM.
+"""CPU oracle for left-side, lower-triangular, no-transpose TRSM, and for the
+general BLAS TRSM (either side, either stored triangle, op(A) = A, A^T, A^H).
 
 TEST INFRASTRUCTURE ONLY.  Only the test-suite, the smoke check and the
 benchmark's CPU-baseline leg may import this package.  The GPU library never
@@ -61,6 +62,15 @@ def _bind(lib):
     lib.oracle_backward_error_z.argtypes = [c_int, i64, i64, dp, dp, i64,
                                             dp, i64, dp, i64, dp]
     lib.oracle_backward_error_z.restype = ctypes.c_double
+    for name in ("oracle_trsm_general_d",):
+        f = getattr(lib, name)
+        f.argtypes = [c_int, c_int, c_int, c_int, i64, i64, ctypes.c_double, dp, i64, dp, i64]
+        f.restype = None
+    lib.oracle_trsm_general_z.argtypes = [c_int, c_int, c_int, c_int, i64, i64, dp, dp, i64, dp, i64]
+    lib.oracle_trsm_general_z.restype = None
+    lib.oracle_backward_error_general.argtypes = [c_int, c_int, c_int, c_int, c_int, i64, i64, dp,
+                                                  dp, i64, dp, i64, dp, i64, dp]
+    lib.oracle_backward_error_general.restype = ctypes.c_double
     lib.oracle_num_threads.argtypes = []
     lib.oracle_num_threads.restype = c_int
     lib.oracle_set_num_threads.argtypes = [c_int]
@@ -170,6 +180,90 @@ class OracleLib:
                                                _ptr(L), _ld(L), _ptr(X), _ld(X),
                                                _ptr(B0), _ld(B0), _ptr(R))
         raise TypeError("X must be float64 or complex128")
+
+
+    def trsm_general(self, A, B, alpha=1.0, side="L", uplo="L", trans="N", unit=False):
+        """General BLAS TRSM in place on B: op(A) X = alpha B (side "L") or
+        X op(A) = alpha B (side "R"); ``uplo`` names the stored triangle of A and
+        ``trans`` is "N", "T" or "C" (conjugate transpose).  Direct substitution
+        on op(A) (trsm_oracle.c, "The general BLAS TRSM")."""
+        lib = self.lib
+        sd, ul, tr = _general_codes(side, uplo, trans)
+        m, n = _general_shapes(A, B, sd)
+        if B.dtype == np.float64:
+            _check_fortran("A", A, np.float64)
+            _check_fortran("B", B, np.float64)
+            if np.imag(alpha) != 0:
+                raise ValueError("complex alpha for real data")
+            lib.oracle_trsm_general_d(sd, ul, tr, int(bool(unit)), m, n, float(np.real(alpha)),
+                                      _ptr(A), _ld(A), _ptr(B), _ld(B))
+            return B
+        if B.dtype == np.complex128:
+            _check_fortran("A", A, np.complex128)
+            _check_fortran("B", B, np.complex128)
+            al = np.array([np.real(alpha), np.imag(alpha)], dtype=np.float64)
+            lib.oracle_trsm_general_z(sd, ul, tr, int(bool(unit)), m, n, _ptr(al), _ptr(A), _ld(A),
+                                      _ptr(B), _ld(B))
+            return B
+        raise TypeError("B must be float64 or complex128")
+
+
+    def solve_general(self, A, B, alpha=1.0, side="L", uplo="L", trans="N", unit=False):
+        """Out-of-place :func:`trsm_general`."""
+        X = np.array(B, dtype=B.dtype, order="F", copy=True)
+        return self.trsm_general(A, X, alpha, side, uplo, trans, unit)
+
+
+    def backward_error_general(self, A, X, B0, alpha=1.0, side="L", uplo="L", trans="N",
+                               unit=False) -> float:
+        """eta = ||R||_inf / (||op(A)||_inf ||X||_inf + |alpha| ||B0||_inf) with
+        R = op(A) X - alpha B0 (left) or X op(A) - alpha B0 (right), Dot2 residual."""
+        lib = self.lib
+        sd, ul, tr = _general_codes(side, uplo, trans)
+        m, n = _general_shapes(A, X, sd)
+        if B0.shape != (m, n):
+            raise ValueError("X and B0 must have the same shape")
+        cx = X.dtype == np.complex128
+        dt = np.complex128 if cx else np.float64
+        for nm, a in (("A", A), ("X", X), ("B0", B0)):
+            _check_fortran(nm, a, dt)
+        R = np.empty((m, n), dtype=dt, order="F")
+        al = np.array([np.real(alpha), np.imag(alpha)], dtype=np.float64)
+        return lib.oracle_backward_error_general(int(cx), sd, ul, tr, int(bool(unit)), m, n, _ptr(al),
+                                                 _ptr(A), _ld(A), _ptr(X), _ld(X), _ptr(B0), _ld(B0),
+                                                 _ptr(R))
+
+
+SIDES = {"L": 0, "R": 1}
+UPLOS = {"L": 0, "U": 1}
+TRANS = {"N": 0, "T": 1, "C": 2}
+
+
+def _general_codes(side, uplo, trans):
+    return SIDES[side.upper()], UPLOS[uplo.upper()], TRANS[trans.upper()]
+
+
+def _general_shapes(A, B, side):
+    m, n = B.shape
+    ka = m if side == 0 else n
+    if A.shape[0] != ka or A.shape[1] < ka:
+        raise ValueError(f"A must be {ka} x {ka}")
+    return m, n
+
+
+def trsm_general(A, B, alpha=1.0, side="L", uplo="L", trans="N", unit=False):
+    """Module-level :meth:`OracleLib.trsm_general` on the default build."""
+    return _load().trsm_general(A, B, alpha, side, uplo, trans, unit)
+
+
+def solve_general(A, B, alpha=1.0, side="L", uplo="L", trans="N", unit=False):
+    """Module-level :meth:`OracleLib.solve_general` on the default build."""
+    return _load().solve_general(A, B, alpha, side, uplo, trans, unit)
+
+
+def backward_error_general(A, X, B0, alpha=1.0, side="L", uplo="L", trans="N", unit=False):
+    """Module-level :meth:`OracleLib.backward_error_general` on the default build."""
+    return _load().backward_error_general(A, X, B0, alpha, side, uplo, trans, unit)
 
 
 def _load() -> OracleLib:

@@ -1,5 +1,7 @@
 /*
- * Reference oracle for left-side, lower-triangular, no-transpose TRSM.
+ * Reference oracle for left-side, lower-triangular, no-transpose TRSM, and for
+ * the general BLAS TRSM (either side, either triangle, op(A) = A, A^T or A^H;
+ * see the section "The general BLAS TRSM" below).
  *
  * TEST INFRASTRUCTURE ONLY.  This file is the plain, slow, obviously correct
  * CPU statement of what the GPU library computes.  Only the test-suite, the
@@ -342,6 +344,245 @@ double oracle_backward_error_z(int unit, int64_t m, int64_t n, const double *alp
     const double rn = z_norm_inf_general(m, n, R, m);
     const double den = z_norm_inf_lower(unit, m, A, lda) * z_norm_inf_general(m, n, X, ldx)
                      + hypot(alpha[0], alpha[1]) * z_norm_inf_general(m, n, B0, ldb);
+    return den > 0.0 ? rn / den : rn;
+}
+
+/* ------------------------------------------------------------------ */
+/* The general BLAS TRSM: op(A) X = alpha B or X op(A) = alpha B        */
+/* ------------------------------------------------------------------ */
+/*
+ * The paper poses the problem as op(A) X = alpha B with A triangular (Sec.
+ * 2.1); its kernels treat the left-side, lower, no-transpose case.  These
+ * functions state every case directly from that definition, by substitution
+ * on op(A) itself, with nothing reduced to the lower-left case (the library
+ * reduces them by transposition and index reversal; the oracle must not share
+ * that reasoning):
+ *
+ *   side  0 = left  (op(A) X = alpha B, A is m x m),
+ *         1 = right (X op(A) = alpha B, A is n x n);
+ *   uplo  0 = A's lower triangle is stored, 1 = its upper triangle;
+ *   trans 0 = op(A) = A, 1 = A^T, 2 = A^H (conjugate transpose; for real
+ *         data the same as 1);
+ *   unit  1 = the diagonal of A is taken as 1 and never read.
+ *
+ * Only the stored triangle of A is read.  op(A) is upper triangular when the
+ * upper triangle is stored and not transposed, or the lower one is stored and
+ * transposed.  Left side, column j of X: op(A) x = alpha b, solved by the dot
+ * form of substitution, top to bottom when op(A) is lower and bottom to top
+ * when it is upper:
+ *     x_i = (alpha b_i - sum_k op(A)_ik x_k) / op(A)_ii,
+ * k over the already solved rows.  Right side, row i of X: sum_k x_ik
+ * op(A)_kj = alpha b_ij for every j, solved left to right when op(A) is upper
+ * (x_ij needs x_ik, k < j) and right to left when it is lower.
+ */
+
+/* op(A)_rc for real data: A_rc, or A_cr when transposed. */
+static inline double d_op(int trans, const double *A, int64_t lda, int64_t r, int64_t c)
+{
+    return trans ? A[c + r * lda] : A[r + c * lda];
+}
+
+/* op(A)_rc for complex data, conjugated for trans == 2. */
+static inline void z_op(int trans, const double *A, int64_t lda, int64_t r, int64_t c,
+                        double *re, double *im)
+{
+    const double *a = trans ? A + 2 * (c + r * lda) : A + 2 * (r + c * lda);
+    *re = a[0];
+    *im = trans == 2 ? -a[1] : a[1];
+}
+
+static inline int op_is_upper(int uplo, int trans)
+{
+    return (uplo == 1) == (trans == 0);
+}
+
+void oracle_trsm_general_d(int side, int uplo, int trans, int unit, int64_t m, int64_t n,
+                           double alpha, const double *A, int64_t lda, double *B, int64_t ldb)
+{
+    if (m <= 0 || n <= 0) return;
+    if (alpha == 0.0) {
+        for (int64_t j = 0; j < n; ++j)
+            for (int64_t i = 0; i < m; ++i) B[i + j * ldb] = 0.0;
+        return;
+    }
+    const int upper = op_is_upper(uplo, trans);
+    if (side == 0) {
+#pragma omp parallel for schedule(dynamic, 1)
+        for (int64_t j = 0; j < n; ++j) {
+            double *x = B + j * ldb;
+            for (int64_t t = 0; t < m; ++t) {
+                const int64_t i = upper ? m - 1 - t : t;
+                double s = alpha * x[i];
+                if (upper)
+                    for (int64_t k = i + 1; k < m; ++k) s = s - d_op(trans, A, lda, i, k) * x[k];
+                else
+                    for (int64_t k = 0; k < i; ++k) s = s - d_op(trans, A, lda, i, k) * x[k];
+                x[i] = unit ? s : s / d_op(trans, A, lda, i, i);
+            }
+        }
+    } else {
+#pragma omp parallel for schedule(dynamic, 1)
+        for (int64_t i = 0; i < m; ++i) {
+            for (int64_t t = 0; t < n; ++t) {
+                const int64_t j = upper ? t : n - 1 - t;
+                double s = alpha * B[i + j * ldb];
+                if (upper)
+                    for (int64_t k = 0; k < j; ++k) s = s - B[i + k * ldb] * d_op(trans, A, lda, k, j);
+                else
+                    for (int64_t k = j + 1; k < n; ++k) s = s - B[i + k * ldb] * d_op(trans, A, lda, k, j);
+                B[i + j * ldb] = unit ? s : s / d_op(trans, A, lda, j, j);
+            }
+        }
+    }
+}
+
+void oracle_trsm_general_z(int side, int uplo, int trans, int unit, int64_t m, int64_t n,
+                           const double *alpha, const double *A, int64_t lda, double *B,
+                           int64_t ldb)
+{
+    if (m <= 0 || n <= 0) return;
+    if (alpha[0] == 0.0 && alpha[1] == 0.0) {
+        for (int64_t j = 0; j < n; ++j)
+            for (int64_t i = 0; i < 2 * m; ++i) B[i + 2 * j * ldb] = 0.0;
+        return;
+    }
+    const int upper = op_is_upper(uplo, trans);
+    if (side == 0) {
+#pragma omp parallel for schedule(dynamic, 1)
+        for (int64_t j = 0; j < n; ++j) {
+            double *x = B + 2 * j * ldb;
+            for (int64_t t = 0; t < m; ++t) {
+                const int64_t i = upper ? m - 1 - t : t;
+                double sr, si, ar, ai, pr, pi;
+                z_mul(alpha[0], alpha[1], x[2 * i], x[2 * i + 1], &sr, &si);
+                const int64_t k0 = upper ? i + 1 : 0, k1 = upper ? m : i;
+                for (int64_t k = k0; k < k1; ++k) {
+                    z_op(trans, A, lda, i, k, &ar, &ai);
+                    z_mul(ar, ai, x[2 * k], x[2 * k + 1], &pr, &pi);
+                    sr = sr - pr;
+                    si = si - pi;
+                }
+                if (unit) {
+                    x[2 * i] = sr;
+                    x[2 * i + 1] = si;
+                } else {
+                    z_op(trans, A, lda, i, i, &ar, &ai);
+                    z_div(sr, si, ar, ai, &x[2 * i], &x[2 * i + 1]);
+                }
+            }
+        }
+    } else {
+#pragma omp parallel for schedule(dynamic, 1)
+        for (int64_t i = 0; i < m; ++i) {
+            for (int64_t t = 0; t < n; ++t) {
+                const int64_t j = upper ? t : n - 1 - t;
+                double sr, si, ar, ai, pr, pi;
+                double *b = B + 2 * (i + j * ldb);
+                z_mul(alpha[0], alpha[1], b[0], b[1], &sr, &si);
+                const int64_t k0 = upper ? 0 : j + 1, k1 = upper ? j : n;
+                for (int64_t k = k0; k < k1; ++k) {
+                    z_op(trans, A, lda, k, j, &ar, &ai);
+                    const double *xk = B + 2 * (i + k * ldb);
+                    z_mul(xk[0], xk[1], ar, ai, &pr, &pi);
+                    sr = sr - pr;
+                    si = si - pi;
+                }
+                if (unit) {
+                    b[0] = sr;
+                    b[1] = si;
+                } else {
+                    z_op(trans, A, lda, j, j, &ar, &ai);
+                    z_div(sr, si, ar, ai, &b[0], &b[1]);
+                }
+            }
+        }
+    }
+}
+
+/*
+ * Normwise backward error of the general problem,
+ *   eta = ||R||_inf / (||op(A)||_inf ||X||_inf + |alpha| ||B0||_inf),
+ *   R = op(A) X - alpha B0 (left) or X op(A) - alpha B0 (right),
+ * with every element of R formed by Dot2 over the triangle of op(A) (the
+ * diagonal taken as 1 when unit) and ||op(A)||_inf the largest row sum of
+ * |op(A)|.  cx selects interleaved complex data (alpha then points to
+ * {re, im}); R is caller scratch of m x n elements.
+ */
+double oracle_backward_error_general(int cx, int side, int uplo, int trans, int unit,
+                                     int64_t m, int64_t n, const double *alpha,
+                                     const double *A, int64_t lda, const double *X,
+                                     int64_t ldx, const double *B0, int64_t ldb, double *R)
+{
+    if (m <= 0 || n <= 0) return 0.0;
+    const int upper = op_is_upper(uplo, trans);
+    const int64_t ka = side == 0 ? m : n;
+    const int es = cx ? 2 : 1;
+    /* op(A)_rc as (re, im); zero outside the triangle, 1 on a unit diagonal */
+#define OPEL(r, c, re, im)                                                         \
+    do {                                                                           \
+        const int64_t r_ = (r), c_ = (c);                                          \
+        if (upper ? (r_ > c_) : (r_ < c_)) { re = 0.0; im = 0.0; }                 \
+        else if (r_ == c_ && unit) { re = 1.0; im = 0.0; }                         \
+        else if (cx) z_op(trans, A, lda, r_, c_, &re, &im);                        \
+        else { re = d_op(trans, A, lda, r_, c_); im = 0.0; }                       \
+    } while (0)
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t j = 0; j < n; ++j) {
+        for (int64_t i = 0; i < m; ++i) {
+            dot2_t re = {0.0, 0.0}, im = {0.0, 0.0};
+            for (int64_t k = 0; k < ka; ++k) {
+                double ar, ai, xr, xi;
+                if (side == 0) {
+                    OPEL(i, k, ar, ai);
+                    xr = X[es * (k + j * ldx)];
+                    xi = cx ? X[es * (k + j * ldx) + 1] : 0.0;
+                } else {
+                    OPEL(k, j, ar, ai);
+                    xr = X[es * (i + k * ldx)];
+                    xi = cx ? X[es * (i + k * ldx) + 1] : 0.0;
+                }
+                if (ar == 0.0 && ai == 0.0) continue;
+                dot2_add_prod(&re, ar, xr);
+                if (cx) {
+                    dot2_add_prod(&re, -ai, xi);
+                    dot2_add_prod(&im, ar, xi);
+                    dot2_add_prod(&im, ai, xr);
+                }
+            }
+            const double br = B0[es * (i + j * ldb)], bi = cx ? B0[es * (i + j * ldb) + 1] : 0.0;
+            dot2_add_prod(&re, -alpha[0], br);
+            if (cx) {
+                dot2_add_prod(&re, alpha[1], bi);
+                dot2_add_prod(&im, -alpha[0], bi);
+                dot2_add_prod(&im, -alpha[1], br);
+            }
+            R[es * (i + j * m)] = dot2_value(&re);
+            if (cx) R[es * (i + j * m) + 1] = dot2_value(&im);
+        }
+    }
+    double rn = 0.0, xn = 0.0, bn = 0.0, an = 0.0;
+    for (int64_t i = 0; i < m; ++i) {
+        double sr = 0.0, sx = 0.0, sb = 0.0;
+        for (int64_t j = 0; j < n; ++j) {
+            sr += cx ? hypot(R[2 * (i + j * m)], R[2 * (i + j * m) + 1]) : fabs(R[i + j * m]);
+            sx += cx ? hypot(X[2 * (i + j * ldx)], X[2 * (i + j * ldx) + 1]) : fabs(X[i + j * ldx]);
+            sb += cx ? hypot(B0[2 * (i + j * ldb)], B0[2 * (i + j * ldb) + 1]) : fabs(B0[i + j * ldb]);
+        }
+        if (sr > rn || isnan(sr)) rn = sr;
+        if (sx > xn || isnan(sx)) xn = sx;
+        if (sb > bn || isnan(sb)) bn = sb;
+    }
+    for (int64_t r = 0; r < ka; ++r) {
+        double s = 0.0;
+        for (int64_t c = 0; c < ka; ++c) {
+            double ar, ai;
+            OPEL(r, c, ar, ai);
+            s += cx ? hypot(ar, ai) : fabs(ar);
+        }
+        if (s > an || isnan(s)) an = s;
+    }
+#undef OPEL
+    const double den = an * xn + (cx ? hypot(alpha[0], alpha[1]) : fabs(alpha[0])) * bn;
     return den > 0.0 ? rn / den : rn;
 }
 

@@ -294,8 +294,220 @@ def pin_backward_error_checker(orc):
         assert abs(eta - num / den) <= 1e-14 * (num / den), (cx, eta, num / den)
 
 
+# ---------------------------------------------------------------------------
+# The general BLAS TRSM: op(A) X = alpha B (left) or X op(A) = alpha B
+# (right), A's lower or upper triangle stored, op(A) = A, A^T or A^H.
+# ---------------------------------------------------------------------------
+VARIANTS = [(side, uplo, trans) for side in "LR" for uplo in "LU" for trans in "NTC"]
+
+
+def _stored(M_lower, uplo):
+    """A holding the lower-triangular M (uplo "L") or its transpose M^T, an
+    upper-triangular matrix (uplo "U"); the other triangle stays NaN."""
+    A = M_lower if uplo == "L" else M_lower.T
+    return np.asfortranarray(A.copy())
+
+
+def _dense_op(A, uplo, trans):
+    """op(A) as a dense array with zeros outside the stored triangle."""
+    k = A.shape[0]
+    Z = np.where(np.tril(np.ones((k, k), bool)) if uplo == "L" else np.triu(np.ones((k, k), bool)),
+                 A, 0)
+    if trans == "N":
+        return Z
+    if trans == "T":
+        return Z.T
+    return Z.conj().T
+
+
+def _op_is_lower(uplo, trans):
+    return (uplo == "L") == (trans == "N")
+
+
+def pin_general_bidiagonal(orc):
+    """op(A) bidiagonal, d'(I - S) or d'(I - S^T) (S the sub-diagonal shift),
+    has inverse (1/d') times the lower or upper all-ones triangle, so X is a
+    running sum of B: down the rows on the left, along the columns on the
+    right, from the end the triangle starts at.  Exact with integer B."""
+    rng = np.random.default_rng(110)
+    for side, uplo, trans in VARIANTS:
+        for cx in (False, True):
+            d = (1 + 1j) if cx else 4.0
+            alpha = 1.0 if cx else 2.0
+            for m, n in ((1, 3), (5, 4), (29, 6)):
+                k = m if side == "L" else n
+                A = _stored(W.bidiagonal_lower(k, d, complex_=cx), uplo)
+                B = W.integer_rhs(rng, m, n, -100, 100, complex_=cx)
+                X = orc.solve_general(A, B, alpha, side, uplo, trans)
+                dp = np.conj(d) if trans == "C" else d
+                scale = alpha / dp      # exact: 0.5, (1 -/+ i)/2
+                ax = 0 if side == "L" else 1
+                lower = _op_is_lower(uplo, trans)
+                # left: lower -> prefix sums, upper -> suffix sums (down the rows);
+                # right: lower -> suffix sums, upper -> prefix sums (along a row)
+                prefix = lower if side == "L" else not lower
+                S = np.cumsum(B, axis=ax) if prefix else \
+                    np.flip(np.cumsum(np.flip(B, axis=ax), axis=ax), axis=ax)
+                assert _bits_equal(X, S * scale), ("general bidiagonal", side, uplo, trans, cx, m, n)
+
+
+def pin_general_block_nilpotent(orc):
+    """op(A) = I + N with N^2 = 0 (A = [[I, 0], [C, I]] or its transpose)
+    has inverse I - N = 2I - op(A), so X = alpha (2I - op(A)) B on the left and
+    alpha B (2I - op(A)) on the right, exactly for integer data; also with a
+    NaN unit diagonal that must not be read."""
+    rng = np.random.default_rng(111)
+    for side, uplo, trans in VARIANTS:
+        for cx in (False, True):
+            for m1, m2, other in ((3, 4, 5), (17, 12, 6)):
+                k = m1 + m2
+                C = W.integer_rhs(rng, m2, m1, -3, 3, complex_=cx)
+                A = _stored(W.block_nilpotent(m1, m2, C), uplo)
+                m, n = (k, other) if side == "L" else (other, k)
+                B = W.integer_rhs(rng, m, n, -20, 20, complex_=cx)
+                alpha = -1.0
+                inv = 2 * np.eye(k) - _dense_op(A, uplo, trans)
+                expect = alpha * (inv @ B if side == "L" else B @ inv)
+                X = orc.solve_general(A, B, alpha, side, uplo, trans)
+                assert _bits_equal(X, expect), ("general nilpotent", side, uplo, trans, cx)
+                Au = A.copy(order="F")
+                Au[np.diag_indices(k)] = np.nan
+                Xu = orc.solve_general(Au, B, alpha, side, uplo, trans, unit=True)
+                assert _bits_equal(Xu, expect), ("general nilpotent unit", side, uplo, trans, cx)
+
+
+def pin_general_bruteforce_rational(orc):
+    """Every variant on tiny dyadic real problems against the exact rational
+    solution (inverse by Cramer's rule): componentwise residual within
+    gamma_{k+1}(|op(A)||X| + |alpha B|), which bounds the forward error."""
+    rng = np.random.default_rng(112)
+    for t, (side, uplo, trans) in enumerate(VARIANTS * 2):
+        m = int(rng.integers(1, 5))
+        n = int(rng.integers(1, 5))
+        k = m if side == "L" else n
+        M = np.zeros((k, k))
+        for i in range(k):
+            for j in range(i):
+                M[i, j] = rng.integers(-16, 17) / 16.0
+            M[i, i] = rng.choice([0.5, 0.75, 1.25, 1.5, 3.0, -2.0])
+        Ml = M.copy()
+        Ml[np.triu_indices(k, 1)] = np.nan
+        A = _stored(Ml, uplo)
+        Bf = rng.integers(-64, 65, size=(m, n)) / 8.0
+        alpha = float(rng.choice([1.0, -0.5, 3.0]))
+        X = orc.solve_general(A, np.asfortranarray(Bf), alpha, side, uplo, trans)
+        Op = _dense_op(A, uplo, trans)
+        Oq = [[Fraction(Op[i, j]) for j in range(k)] for i in range(k)]
+        det = _det(Oq)
+        inv = [[None] * k for _ in range(k)]
+        for c in range(k):
+            for r in range(k):
+                Mi = [row[:] for row in Oq]
+                for q in range(k):
+                    Mi[q][r] = Fraction(int(q == c))
+                inv[r][c] = _det(Mi) / det
+        gamma = Fraction(k + 1) * Fraction(U) / (1 - (k + 1) * Fraction(U))
+        Xq = [[Fraction(X[i, j]) for j in range(n)] for i in range(m)]
+        Bq = [[Fraction(alpha) * Fraction(Bf[i, j]) for j in range(n)] for i in range(m)]
+        if side == "L":
+            res = [[sum(Oq[i][q] * Xq[q][j] for q in range(k)) - Bq[i][j] for j in range(n)]
+                   for i in range(m)]
+            cap = [[gamma * (sum(abs(Oq[i][q]) * abs(Xq[q][j]) for q in range(k)) + abs(Bq[i][j]))
+                    for j in range(n)] for i in range(m)]
+            exact = [[sum(inv[i][q] * Bq[q][j] for q in range(k)) for j in range(n)] for i in range(m)]
+            fe = [[sum(abs(inv[i][q]) * cap[q][j] for q in range(k)) for j in range(n)]
+                  for i in range(m)]
+        else:
+            res = [[sum(Xq[i][q] * Oq[q][j] for q in range(k)) - Bq[i][j] for j in range(n)]
+                   for i in range(m)]
+            cap = [[gamma * (sum(abs(Xq[i][q]) * abs(Oq[q][j]) for q in range(k)) + abs(Bq[i][j]))
+                    for j in range(n)] for i in range(m)]
+            exact = [[sum(Bq[i][q] * inv[q][j] for q in range(k)) for j in range(n)] for i in range(m)]
+            fe = [[sum(cap[i][q] * abs(inv[q][j]) for q in range(k)) for j in range(n)]
+                  for i in range(m)]
+        for i in range(m):
+            for j in range(n):
+                assert abs(res[i][j]) <= cap[i][j], ("general residual", t, side, uplo, trans, i, j)
+                assert abs(Xq[i][j] - exact[i][j]) <= fe[i][j], ("general forward", t, side, uplo, trans)
+
+
+def pin_general_library(orc):
+    """Every variant against LAPACK trtrs (scipy): left side directly; right
+    side through X op(A) = alpha B  <=>  op(A)^T X^T = alpha B^T."""
+    import scipy.linalg as sl
+    for side, uplo, trans in VARIANTS:
+        for cx in (False, True):
+            for unit in (False, True):
+                for m, n in ((17, 9), (120, 40)):
+                    k = m if side == "L" else n
+                    Lk, _ = W.problem(8 + k, k, 1, cx)
+                    B = W.rhs_matrix(np.random.default_rng(9 + m + n), m, n, cx)
+                    A = _stored(Lk, uplo)
+                    Z = np.nan_to_num(A, nan=0.0)
+                    alpha = complex(1.0, 0.5) if cx else -1.25
+                    X = orc.solve_general(A, B, alpha, side, uplo, trans, unit)
+                    if side == "L":
+                        ref = sl.solve_triangular(Z, alpha * B, lower=uplo == "L", trans=trans,
+                                                  unit_diagonal=unit, check_finite=False)
+                    elif trans == "N":
+                        ref = sl.solve_triangular(Z, alpha * B.T, lower=uplo == "L", trans="T",
+                                                  unit_diagonal=unit, check_finite=False).T
+                    elif trans == "T":
+                        ref = sl.solve_triangular(Z, alpha * B.T, lower=uplo == "L", trans="N",
+                                                  unit_diagonal=unit, check_finite=False).T
+                    else:
+                        ref = sl.solve_triangular(Z.conj(), alpha * B.T, lower=uplo == "L",
+                                                  trans="N", unit_diagonal=unit,
+                                                  check_finite=False).T
+                    rel = np.linalg.norm(X - ref) / np.linalg.norm(ref)
+                    assert rel <= 1e-13, ("general scipy", side, uplo, trans, cx, unit, rel)
+
+
+def pin_general_consistency(orc):
+    """The left, lower, no-transpose case of the general solver is the
+    oracle's row form, bit for bit (the same order of operations)."""
+    for cx in (False, True):
+        for unit in (False, True):
+            L, B = W.problem(31, 70, 13, cx)
+            alpha = complex(0.5, 2.0) if cx else 0.75
+            X = orc.solve_general(L, B, alpha, "L", "L", "N", unit)
+            Xr = orc.solve(L, B, alpha, unit=unit, rowform=True)
+            assert X.tobytes() == np.asfortranarray(Xr).tobytes(), ("general vs row form", cx, unit)
+            Bn = np.full((13, 70), np.nan, dtype=B.dtype, order="F")
+            Ln = np.full(L.shape, np.nan, dtype=L.dtype, order="F")
+            Z = orc.solve_general(Ln, Bn, 0.0, "R", "U", "C", unit)
+            assert np.all(Z == 0), "alpha = 0 reads nothing"
+
+
+def pin_general_backward_error_checker(orc):
+    """Hand-computed values of the general checker (chosen so that a wrong
+    index, a dropped absolute value or a dropped conjugation changes them)."""
+    F = lambda a, dt=np.float64: np.asfortranarray(np.array(a, dtype=dt))
+    nan = np.nan
+    # left, lower, N: A = [[2, .], [-1, 4]], X = [1; 1], B = [3; 6]:
+    # A X - B = [-1; -3], ||A|| = 5, eta = 3 / (5 * 1 + 1 * 6) = 3/11
+    A = F([[2.0, nan], [-1.0, 4.0]])
+    eta = orc.backward_error_general(A, F([[1.0], [1.0]]), F([[3.0], [6.0]]), 1.0, "L", "L", "N")
+    assert abs(eta - 3.0 / 11.0) <= 1e-15, eta
+    # right, lower, T: op(A) = A^T = [[2, -1], [0, 4]], X = [1 2], B = [3 6]:
+    # X op(A) = [2 7], R = [-1 1], ||op(A)|| = 4, eta = 2 / (4 * 3 + 9) = 2/21
+    eta = orc.backward_error_general(A, F([[1.0, 2.0]]), F([[3.0, 6.0]]), 1.0, "R", "L", "T")
+    assert abs(eta - 2.0 / 21.0) <= 1e-15, eta
+    # complex, left, lower, C: A = [[2, .], [i, 4]], op(A) = A^H = [[2, -i], [0, 4]],
+    # X = [1; 1], alpha = i, B = [1; -4i]: op(A) X = [2 - i; 4], alpha B = [i; 4],
+    # R = [2 - 2i; 0], eta = sqrt(8) / (4 * 1 + 1 * 4)
+    Ac = F([[2.0, nan], [1j, 4.0]], np.complex128)
+    X = F([[1.0], [1.0]], np.complex128)
+    B = F([[1.0], [-4j]], np.complex128)
+    eta = orc.backward_error_general(Ac, X, B, 1j, "L", "L", "C")
+    assert abs(eta - np.sqrt(8.0) / 8.0) <= 1e-15, eta
+
+
+# Cheap pins first: the mutant test stops at the first pin that fails.
 ALL_PINS = [
     pin_identity, pin_diagonal, pin_bidiagonal, pin_block_nilpotent,
-    pin_integer_roundtrip, pin_bruteforce_rational, pin_library, pin_invariants,
-    pin_alpha_zero, pin_backward_error_checker,
+    pin_integer_roundtrip, pin_alpha_zero, pin_backward_error_checker,
+    pin_general_bidiagonal, pin_general_block_nilpotent, pin_general_consistency,
+    pin_general_backward_error_checker, pin_general_bruteforce_rational,
+    pin_bruteforce_rational, pin_invariants, pin_library, pin_general_library,
 ]

@@ -37,6 +37,28 @@ MUTATIONS = {
     "residual_dropped_diag": ("dot2_add_prod(&acc, unit ? 1.0 : A[i + i * lda], x[i]);", ""),
     "norm_of_X_wrong": ("d_norm_inf_lower(unit, m, A, lda) * d_norm_inf_general(m, n, X, ldx)",
                         "d_norm_inf_lower(unit, m, A, lda) * d_norm_inf_general(m, n, B0, ldb)"),
+    # the general solver (either side, either triangle, op(A) = A, A^T, A^H)
+    "general_transpose_ignored": ("return trans ? A[c + r * lda] : A[r + c * lda];",
+                                  "return A[r + c * lda];"),
+    "general_conj_dropped": ("*im = trans == 2 ? -a[1] : a[1];", "*im = a[1];"),
+    "general_upper_rule": ("return (uplo == 1) == (trans == 0);", "return uplo == 1;"),
+    "general_left_direction": ("const int64_t i = upper ? m - 1 - t : t;\n                double s",
+                               "const int64_t i = upper ? t : m - 1 - t;\n                double s"),
+    "general_right_direction": ("const int64_t j = upper ? t : n - 1 - t;\n                double s",
+                                "const int64_t j = upper ? n - 1 - t : t;\n                double s"),
+    "general_right_operand_index": ("s = s - B[i + k * ldb] * d_op(trans, A, lda, k, j);",
+                                    "s = s - B[i + k * ldb] * d_op(trans, A, lda, j, k);"),
+    "general_unit_read": ("x[i] = unit ? s : s / d_op(trans, A, lda, i, i);",
+                          "x[i] = s / d_op(trans, A, lda, i, i);"),
+    "general_left_skips_last": ("for (int64_t k = i + 1; k < m; ++k) s = s - d_op(trans, A, lda, i, k) * x[k];",
+                                "for (int64_t k = i + 2; k < m; ++k) s = s - d_op(trans, A, lda, i, k) * x[k];"),
+    "general_z_right_update_sign": ("                    sr = sr - pr;\n                    si = si - pi;\n                }\n                if (unit) {\n                    b[0] = sr;",
+                                    "                    sr = sr + pr;\n                    si = si - pi;\n                }\n                if (unit) {\n                    b[0] = sr;"),
+    "general_z_alpha_conj": ("z_mul(alpha[0], alpha[1], b[0], b[1], &sr, &si);",
+                             "z_mul(alpha[0], -alpha[1], b[0], b[1], &sr, &si);"),
+    "general_residual_right_index": ("OPEL(k, j, ar, ai);", "OPEL(j, k, ar, ai);"),
+    "general_residual_conj": ("dot2_add_prod(&im, ai, xr);\n                }", "dot2_add_prod(&im, -ai, xr);\n                }"),
+    "general_norm_of_op": ("s += cx ? hypot(ar, ai) : fabs(ar);", "s += cx ? hypot(ar, ai) : ar;"),
 }
 
 
@@ -54,4 +76,5 @@ def test_mutant_is_caught(tmp_path, name):
             pin(orc)
         except (AssertionError, ValueError, FloatingPointError):
             failed.append(pin.__name__)
+            break               # caught; the remaining pins need not run
     assert failed, f"no pin catches the planted mistake {name}"
