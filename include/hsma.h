@@ -127,6 +127,45 @@ hsma_status hsma_trsm_noalloc(hsma_diag diag, int64_t m, int64_t n, const void *
 /* Bytes of the per-device scratch array of hsma_trsm_noalloc. */
 uint64_t hsma_noalloc_scratch_bytes(void);
 
+/* ------------------------------------------------------------------------ */
+/* The general BLAS TRSM: either side, either triangle, op(A) = A, A^T, A^H  */
+/* ------------------------------------------------------------------------ */
+
+typedef enum { HSMA_LEFT = 0, HSMA_RIGHT = 1 } hsma_side;
+typedef enum { HSMA_LOWER = 0, HSMA_UPPER = 1 } hsma_uplo;
+typedef enum { HSMA_OP_N = 0, HSMA_OP_T = 1, HSMA_OP_C = 2 } hsma_op;
+
+/*
+ * hsma_trsm_general -- the problem as the paper poses it, op(A) X = alpha B
+ * (Sec. 2.1), in every BLAS form: X overwrites B, where
+ *   side  HSMA_LEFT:  op(A) X = alpha B, A is m x m (lda >= max(1, m));
+ *         HSMA_RIGHT: X op(A) = alpha B, A is n x n (lda >= max(1, n));
+ *   uplo  which triangle of A is stored (only that one is read);
+ *   trans op(A) = A, A^T or A^H (the conjugate transpose; for real data the
+ *         same as A^T);
+ *   diag  HSMA_UNIT: the diagonal of A is taken as 1 and not read.
+ * B is m x n, column-major (ldb >= max(1, m)); alpha is a host pointer as for
+ * hsma_trsm (not conjugated by trans).  Left, lower, no transpose is
+ * hsma_trsm itself.  Every other case runs the same small and blocked
+ * kernels on re-indexed copies (all device work on `stream`): the effective
+ * operator (op(A), or op(A)^T for the right side) is copied into a
+ * lower-triangular workspace, its indices reversed when it is upper
+ * triangular, and B into a workspace with its rows reversed and, for the
+ * right side, transposed (for left-side cases whose operator is lower, B is
+ * solved in place); the solve's result is copied back.  The workspace holds
+ * k^2 (+ m n) elements, k the order of A.
+ * Errors, in this order: side, uplo, trans, diag or dtype not an enumerator
+ * -> HSMA_INVALID_VALUE; m < 0 or n < 0 -> HSMA_INVALID_SIZE; lda or ldb too
+ * small -> HSMA_INVALID_SIZE; m == 0 or n == 0 -> HSMA_SUCCESS, nothing done;
+ * alpha NULL -> HSMA_INVALID_POINTER; B NULL, or A NULL with alpha != 0 ->
+ * HSMA_INVALID_POINTER.  alpha == 0 zero-fills B without reading A or B.
+ * Asynchronous on `stream`.
+ */
+hsma_status hsma_trsm_general(hsma_side side, hsma_uplo uplo, hsma_op trans, hsma_diag diag,
+                              int64_t m, int64_t n, const void *alpha, const void *A,
+                              int64_t lda, void *B, int64_t ldb, hsma_dtype dtype,
+                              hsma_stream_t stream);
+
 /* Precision of the blocked path's trailing updates. */
 typedef enum {
     HSMA_PREC_FP64 = 0,   /* everything in FP64 (FP64 matrix cores) */

@@ -135,6 +135,8 @@ def lib():
         L.hsma_trsm_ex.argtypes = [i32, i64, i64, vp, vp, i64, vp, i64, i32,
                                    ctypes.POINTER(TrsmOptions), ctypes.POINTER(TrsmReport), vp]
         L.hsma_trsm_ex.restype = i32
+        L.hsma_trsm_general.argtypes = [i32, i32, i32, i32, i64, i64, vp, vp, i64, vp, i64, i32, vp]
+        L.hsma_trsm_general.restype = i32
         L.hsma_trsm_noalloc.argtypes = [i32, i64, i64, vp, vp, i64, vp, i64, i32, vp]
         L.hsma_trsm_noalloc.restype = i32
         L.hsma_noalloc_scratch_bytes.argtypes = []
@@ -310,6 +312,35 @@ def trsm(L, B, alpha=1.0, unit: bool = False, block_size: int = 0, path: int = 0
     if report:
         return B, {"path": rep.path, "block_size": rep.block_size,
                    "refine_steps": rep.refine_steps, "backward_error": rep.backward_error}
+    return B
+
+
+SIDE = {"L": 0, "R": 1}
+UPLO = {"L": 0, "U": 1}
+OP = {"N": 0, "T": 1, "C": 2}
+
+
+def trsm_general(A, B, alpha=1.0, side: str = "L", uplo: str = "L", trans: str = "N",
+                 unit: bool = False, stream=None):
+    """B <- X with op(A) X = alpha B (side "L") or X op(A) = alpha B (side
+    "R"), in place.  ``uplo`` names the stored triangle of A ("L" or "U"),
+    ``trans`` is "N", "T" or "C" (conjugate transpose).  A is k x k with k = m
+    (left) or n (right); both column-major device tensors of one dtype."""
+    code = _dtype_code(B)
+    if A.dtype != B.dtype:
+        raise TypeError("A and B must have the same dtype")
+    m, n = B.shape
+    k = m if side.upper() == "L" else n
+    if A.shape[0] != k or A.shape[1] < k:
+        raise ValueError(f"A must be {k} x {k}")
+    if m and n and (not A.is_cuda or not B.is_cuda):
+        raise ValueError("tensors must be on the GPU")
+    st = lib().hsma_trsm_general(SIDE[side.upper()], UPLO[uplo.upper()], OP[trans.upper()],
+                                 UNIT if unit else NON_UNIT, m, n, _alpha_buf(alpha, code),
+                                 ctypes.c_void_p(A.data_ptr()), leading_dim(A),
+                                 ctypes.c_void_p(B.data_ptr()), leading_dim(B), code,
+                                 ctypes.c_void_p(_stream_handle(stream)))
+    _check(st, "hsma_trsm_general")
     return B
 
 

@@ -203,3 +203,29 @@ def test_noalloc_rejects_oversized_workspace_before_device(lib):
     assert f(0, 0, 1, one, None, 1, None, 1, 0, None) == 0
     assert f(0, 5, 1, None, fake, 5, fake, 5, 0, None) == 3
     assert lib.hsma_status_string(12)
+
+
+def test_general_validation_order_without_device(lib):
+    """hsma_trsm_general checks its arguments in the documented order before
+    any device call (fake pointers are never dereferenced)."""
+    f = lib.hsma_trsm_general
+    i32, i64, vp = ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p
+    f.argtypes = [i32, i32, i32, i32, i64, i64, vp, vp, i64, vp, i64, i32, vp]
+    f.restype = i32
+    one = (ctypes.c_double * 2)(1.0, 0.0)
+    zero = (ctypes.c_double * 2)(0.0, 0.0)
+    A, B = ctypes.c_void_p(16), ctypes.c_void_p(32)
+
+    def call(side=0, uplo=0, trans=0, diag=0, m=4, n=3, alpha=one, A=A, lda=4, B=B, ldb=4, dt=0):
+        return f(side, uplo, trans, diag, m, n, alpha, A, lda, B, ldb, dt, None)
+    assert call(side=2) == 1 and call(uplo=-1) == 1 and call(trans=3) == 1
+    assert call(diag=2) == 1 and call(dt=5) == 1
+    assert call(m=-1) == 2 and call(n=-1) == 2
+    assert call(side=1, lda=2) == 2            # right side: lda >= n = 3
+    assert call(side=0, lda=3) == 2            # left side: lda >= m = 4
+    assert call(ldb=3) == 2
+    assert call(side=1, m=5, n=0, lda=1, ldb=5) == 0
+    assert call(alpha=None) == 3
+    assert call(B=None) == 3
+    assert call(A=None) == 3
+    assert call(side=1, uplo=1, trans=2, A=None, alpha=zero, m=0) == 0
