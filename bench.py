@@ -59,7 +59,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="default",
                     choices=["default", "large_real", "large_complex", "batched", "single", "mixed",
-                             "serving"])
+                             "serving", "variants"])
     ap.add_argument("--ib", type=int, default=0, help="force I_B (0 = tuning table)")
     ap.add_argument("--m", type=int, default=0, help="override m (and n) for sweeps")
     ap.add_argument("--n", type=int, default=0)
@@ -100,6 +100,24 @@ class RocBlas:
         for f in (self.lib.rocblas_dtrsm, self.lib.rocblas_ztrsm):
             f.argtypes = [vp, i32, i32, i32, i32, i32, i32, vp, vp, i32, vp, i32]
             f.restype = i32
+
+    SIDE = {"L": 141, "R": 142}
+    UPLO = {"U": 121, "L": 122}
+    OP = {"N": 111, "T": 112, "C": 113}
+
+    def trsm_general(self, A, B, alpha, side, uplo, trans, unit=False):
+        import torch
+        import paper_2608_25469_amd as hs
+        m, n = B.shape
+        cx = B.dtype == torch.complex128
+        a = (ctypes.c_double * 2)(complex(alpha).real, complex(alpha).imag)
+        f = self.lib.rocblas_ztrsm if cx else self.lib.rocblas_dtrsm
+        st = f(self.h, self.SIDE[side], self.UPLO[uplo], self.OP[trans],
+               self.DIAG_UNIT if unit else self.DIAG_NON_UNIT, m, n, a,
+               ctypes.c_void_p(A.data_ptr()), hs.leading_dim(A),
+               ctypes.c_void_p(B.data_ptr()), hs.leading_dim(B))
+        if st != 0:
+            raise RuntimeError(f"rocblas trsm: {st}")
 
     def trsm(self, L, B, alpha, unit=False):
         import torch
@@ -403,6 +421,80 @@ def run_batched(args, torch, hs, cfg):
     }
 
 
+def run_variants(args, torch, hs, k=8192, reps=3):
+    """The general BLAS TRSM (hsma_trsm_general) on DTRSM m = n = k in every
+    real form (side x stored triangle x op(A)), against rocBLAS's same form,
+    with the share of time spent in the re-indexing copies and an oracle check
+    on sampled columns (left side) or rows (right side)."""
+    import oracle
+    rows = []
+    L, B = W.problem(2, k, k, False)
+    Ld = hs.to_colmajor(L)
+    Ud = hs.to_colmajor(np.asfortranarray(L.T))
+    B0 = hs.to_colmajor(B)
+    Bd = hs.colmajor(k, k, torch.float64)
+    fl = W.flops(k, k, False)
+    try:
+        rb = RocBlas(torch.cuda.current_stream().cuda_stream)
+    except Exception as e:  # reported, not fatal
+        rb = None
+        log(f"rocBLAS unavailable: {e}")
+    for side in "LR":
+        for uplo in "LU":
+            for trans in "NT":
+                A = Ld if uplo == "L" else Ud
+                Ah = L if uplo == "L" else np.asfortranarray(L.T)
+
+                def ours():
+                    hs.trsm_general(A, Bd, -1.0, side=side, uplo=uplo, trans=trans)
+                Bd.copy_(B0)
+                ours()
+                torch.cuda.synchronize()
+                idx = np.unique(np.linspace(0, k - 1, num=4).astype(int)).tolist()
+                if side == "L":
+                    Xs = np.asfortranarray(Bd[:, idx].cpu().numpy())
+                    Bs = np.asfortranarray(B[:, idx])
+                else:
+                    Xs = np.asfortranarray(Bd[idx, :].cpu().numpy())
+                    Bs = np.asfortranarray(B[idx, :])
+                ref = oracle.solve_general(Ah, Bs, -1.0, side, uplo, trans)
+                rel = oracle.rel_err_fro(Xs, ref)
+                ts = []
+                hs.profile_begin()
+                for _ in range(reps):
+                    Bd.copy_(B0)
+                    torch.cuda.synchronize()
+                    t = time.perf_counter()
+                    ours()
+                    torch.cuda.synchronize()
+                    ts.append((time.perf_counter() - t) * 1e3)
+                prof = hs.profile_end()
+                busy = sum(v["ms"] for v in prof.values())
+                ms = min(ts)
+                row = {"side": side, "uplo": uplo, "trans": trans, "ms": round(ms, 3),
+                       "gflops": round(fl / (ms * 1e-3) / 1e9, 1),
+                       "copy_share": round(prof["other"]["ms"] / busy, 4) if busy else None,
+                       "sampled": f"{len(idx)} {'columns' if side == 'L' else 'rows'}",
+                       "rel_err_fro_vs_oracle": rel, "parity_ok": bool(rel <= 1e-12)}
+                if rb is not None:
+                    rts = []
+                    for _ in range(reps):
+                        Bd.copy_(B0)
+                        torch.cuda.synchronize()
+                        t = time.perf_counter()
+                        rb.trsm_general(A, Bd, -1.0, side, uplo, trans)
+                        torch.cuda.synchronize()
+                        rts.append((time.perf_counter() - t) * 1e3)
+                    row["rocblas_ms"] = round(min(rts), 3)
+                    row["speedup_over_rocblas"] = round(min(rts) / ms, 3)
+                rows.append(row)
+                log(f"variant {side}{uplo}{trans} k={k}: {ms:.2f} ms ({row['gflops']} GF/s), "
+                    f"rocBLAS {row.get('rocblas_ms')} ms, copies {row['copy_share']}, rel {rel:.1e}")
+    del Ld, Ud, B0, Bd
+    return {"workload": f"DTRSM m=n={k}, alpha=-1, seed 2, every real (side, uplo, trans)",
+            "flops_per_solve": fl, "rows": rows}
+
+
 def run_graph(args, torch, hs, sizes=(256, 512, 1024), reps=30):
     """Blocked schedule replayed as a captured HIP graph vs launched eagerly,
     on mid-size DTRSMs where launch overhead matters (same inputs, results
@@ -688,6 +780,12 @@ def run_headline(args, torch, hs, names):
     except Exception as e:
         out["single"] = {"error": repr(e)}
     try:
+        out["variants"] = run_variants(sub, torch, hs)
+    except Exception as e:
+        out["variants"] = {"error": repr(e)}
+    torch.cuda.empty_cache()
+    hs.workspace_release()
+    try:
         out["graph"] = run_graph(sub, torch, hs)
     except Exception as e:
         out["graph"] = {"error": repr(e)}
@@ -750,6 +848,13 @@ def main():
         res = run_serving(args, torch, hs)
         workload = (f"TRSM serving: Poisson {args.rate:.0f} req/s for {args.duration:.0f} s, m log-U[8,4096], "
                     f"n log-U[1,512], 70% real / 30% complex, seed 4")
+    elif args.workload == "variants":
+        r = run_variants(args, torch, hs, k=args.m or 8192)
+        first = r["rows"][0]
+        res = {"value": first["gflops"], "unit": "GFLOP/s", "ms_per_step": first["ms"], "dtype": "f64",
+               "pct_fp64_peak": round(100 * first["gflops"] / (FP64_PEAK_TFLOPS * 1e3), 2),
+               "extra_config": {"m": args.m or 8192}, "variants": r}
+        workload = r["workload"]
     elif args.workload == "batched":
         res = run_batched(args, torch, hs, dict(W.BATCHED))
         workload = names["batched"] if not args.count else f"ZTRSM batched: {args.count} solves"
@@ -772,7 +877,7 @@ def main():
                         "flop_convention": "real m^2 n; complex 4 m^2 n + 2 m n"}, **res["extra_config"]),
     }
     for k in ("solves_per_s", "gflops", "phases", "parity", "roofline", "rocblas", "cpu_baseline",
-              "mixed", "serving"):
+              "mixed", "serving", "variants"):
         if k in res:
             out[k] = res[k]
     if headline is not None:
