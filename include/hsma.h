@@ -18,8 +18,11 @@
  *   - alpha == 0 sets B to zero and reads neither A nor B.
  *   - No singularity check: a zero or non-finite diagonal propagates IEEE
  *     infinities/NaNs.
- *   - Real data is IEEE double; complex data is interleaved {double re, im}
- *     (the layout of hipDoubleComplex and torch.complex128).
+ *   - Real data is IEEE double (HSMA_R64F) or float (HSMA_R32F); complex data
+ *     is interleaved {re, im} of double (HSMA_C64F, the layout of
+ *     hipDoubleComplex and torch.complex128) or of float (HSMA_C32F,
+ *     torch.complex64).  FP32 solves compute in FP32 (FP32 matrix cores,
+ *     FP32 accumulation), as STRSM/CTRSM do.
  *
  * Memory and streams:
  *   - A and B are DEVICE pointers owned by the caller.  A and B must not
@@ -50,7 +53,11 @@
 extern "C" {
 #endif
 
-typedef enum { HSMA_R64F = 0, HSMA_C64F = 1 } hsma_dtype;
+/* Data types.  The paper evaluates all four (Sec. 5).  The FP32 ones
+ * (STRSM, CTRSM) are taken by hsma_trsm, hsma_trsm_ex (plain solves) and
+ * hsma_trsm_general; the batched, queue and allocation-free calls take FP64
+ * data only (HSMA_NOT_SUPPORTED otherwise). */
+typedef enum { HSMA_R64F = 0, HSMA_C64F = 1, HSMA_R32F = 2, HSMA_C32F = 3 } hsma_dtype;
 typedef enum { HSMA_NON_UNIT = 0, HSMA_UNIT = 1 } hsma_diag;
 
 typedef enum {
@@ -86,11 +93,12 @@ const char *hsma_version(void);
  *
  *   diag   HSMA_NON_UNIT or HSMA_UNIT (diagonal of A taken as 1, not read).
  *   m, n   rows of A and B / columns of B.
- *   alpha  HOST pointer to a double (HSMA_R64F) or double[2] = {re, im}
- *          (HSMA_C64F); read before the call returns.
+ *   alpha  HOST pointer to one scalar of the data type: double (HSMA_R64F),
+ *          double[2] = {re, im} (HSMA_C64F), float (HSMA_R32F) or float[2]
+ *          (HSMA_C32F); read before the call returns.
  *   A      device pointer, m x m column-major, leading dimension lda.
  *   B      device pointer, m x n column-major, leading dimension ldb; in/out.
- *   dtype  HSMA_R64F or HSMA_C64F.
+ *   dtype  HSMA_R64F, HSMA_C64F, HSMA_R32F or HSMA_C32F.
  *   stream hipStream_t or NULL.
  *
  * Path: m <= 64 uses the register-resident small-solve kernel, one wavefront
@@ -218,7 +226,9 @@ typedef struct {
  * Unknown option values give HSMA_INVALID_VALUE; forcing the small kernel
  * with m > 64 gives HSMA_NOT_SUPPORTED; HSMA_PREC_MIXED with complex data
  * gives HSMA_NOT_SUPPORTED.  Refinement and the backward error work for both
- * data types (complex: the modulus in every row sum and |alpha|).
+ * FP64 data types (complex: the modulus in every row sum and |alpha|).  FP32
+ * data takes plain solves only: the mixed mode, refinement, the backward
+ * error or graph replay with HSMA_R32F/HSMA_C32F give HSMA_NOT_SUPPORTED.
  * Asynchronous on `stream` unless a backward error is needed
  * (want_backward_error = 1 or refine_steps = -1): then the call waits for the
  * stream before returning, because the value decides what happens next.

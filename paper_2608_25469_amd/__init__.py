@@ -22,7 +22,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libhsma.so")
 
-R64F, C64F = 0, 1
+R64F, C64F, R32F, C32F = 0, 1, 2, 3
 NON_UNIT, UNIT = 0, 1
 
 STATUS = {
@@ -226,7 +226,8 @@ def to_colmajor(a: np.ndarray, device="cuda", ld: Optional[int] = None):
     """Copy a 2-D numpy array (any layout) to a column-major device tensor."""
     torch = _torch()
     m, n = a.shape
-    dt = torch.complex128 if np.iscomplexobj(a) else torch.float64
+    dt = {np.dtype(np.float64): torch.float64, np.dtype(np.complex128): torch.complex128,
+          np.dtype(np.float32): torch.float32, np.dtype(np.complex64): torch.complex64}[a.dtype]
     out = colmajor(m, n, dt, ld=ld, device=device)
     if m and n:
         out.copy_(torch.from_numpy(np.ascontiguousarray(a)))
@@ -249,17 +250,20 @@ def leading_dim(t) -> int:
 
 def _dtype_code(t) -> int:
     torch = _torch()
-    if t.dtype == torch.float64:
-        return R64F
-    if t.dtype == torch.complex128:
-        return C64F
-    raise TypeError("tensors must be float64 or complex128")
+    codes = {torch.float64: R64F, torch.complex128: C64F, torch.float32: R32F,
+             torch.complex64: C32F}
+    if t.dtype in codes:
+        return codes[t.dtype]
+    raise TypeError("tensors must be float64, complex128, float32 or complex64")
 
 
 def _alpha_buf(alpha, code):
+    """Host scalar of the data type: double[2] for FP64, float[2] for FP32."""
     a = complex(alpha)
-    if code == R64F and a.imag != 0:
+    if code in (R64F, R32F) and a.imag != 0:
         raise ValueError("complex alpha for a real problem")
+    if code in (R32F, C32F):
+        return (ctypes.c_float * 2)(a.real, a.imag)
     return (ctypes.c_double * 2)(a.real, a.imag)
 
 

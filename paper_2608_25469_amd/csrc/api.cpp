@@ -13,6 +13,9 @@
 namespace hsma {
 
 size_t blocked_workspace_bytes(bool cx, int64_t m, int ib);
+size_t blocked_workspace_bytes32(bool cx, int64_t m, int ib);
+hsma_status blocked_trsm32(bool cx, bool unit, int64_t m, int64_t n, cplx alpha, const float *A,
+                           int64_t lda, float *B, int64_t ldb, int ib, void *ws, hipStream_t s);
 hsma_status blocked_trsm(bool cx, bool unit, int64_t m, int64_t n, cplx alpha, const double *A,
                          int64_t lda, double *B, int64_t ldb, int ib, void *ws, hipStream_t s,
                          bool mixed);
@@ -101,12 +104,28 @@ bool valid_block_size(bool cx, int ib) {
     return ib == 16 || ib == 32 || ib == 64 || ib == 128 || ib == 256;
 }
 
+bool is_single(int dtype) { return dtype == HSMA_R32F || dtype == HSMA_C32F; }
+bool is_complex(int dtype) { return dtype == HSMA_C64F || dtype == HSMA_C32F; }
+
+// alpha as read from the caller's host scalar of the data type.
+cplx read_alpha(int dtype, const void *alpha) {
+    if (is_single(dtype)) {
+        const float *a = static_cast<const float *>(alpha);
+        return cplx{(double)a[0], dtype == HSMA_C32F ? (double)a[1] : 0.0};
+    }
+    const double *a = static_cast<const double *>(alpha);
+    return cplx{a[0], dtype == HSMA_C64F ? a[1] : 0.0};
+}
+
 // Argument checks in the documented order; nothing touches the device.
+// FP32 data types are accepted only where allow32 (else HSMA_NOT_SUPPORTED).
 hsma_status validate(int diag, int dtype, int64_t m, int64_t n, const void *alpha, const void *A,
-                     int64_t lda, const void *B, int64_t ldb, bool *quick) {
+                     int64_t lda, const void *B, int64_t ldb, bool *quick, bool allow32) {
     *quick = false;
-    if ((diag != HSMA_NON_UNIT && diag != HSMA_UNIT) || (dtype != HSMA_R64F && dtype != HSMA_C64F))
+    if ((diag != HSMA_NON_UNIT && diag != HSMA_UNIT) ||
+        (dtype != HSMA_R64F && dtype != HSMA_C64F && !is_single(dtype)))
         return HSMA_INVALID_VALUE;
+    if (is_single(dtype) && !allow32) return HSMA_NOT_SUPPORTED;
     if (m < 0 || n < 0) return HSMA_INVALID_SIZE;
     const int64_t lo = m > 1 ? m : 1;
     if (lda < lo || ldb < lo) return HSMA_INVALID_SIZE;
@@ -115,8 +134,8 @@ hsma_status validate(int diag, int dtype, int64_t m, int64_t n, const void *alph
         return HSMA_SUCCESS;
     }
     if (!alpha) return HSMA_INVALID_POINTER;
-    const double *a = static_cast<const double *>(alpha);
-    const bool azero = (a[0] == 0.0) && (dtype == HSMA_R64F || a[1] == 0.0);
+    const cplx a = read_alpha(dtype, alpha);
+    const bool azero = a.re == 0.0 && a.im == 0.0;
     if (!B || (!A && !azero)) return HSMA_INVALID_POINTER;
     // Largest index must fit the kernels' 64-bit arithmetic and int grids.
     if (m > (int64_t)1 << 30 || n > (int64_t)1 << 40) return HSMA_INVALID_SIZE;
@@ -144,6 +163,30 @@ static hsma_status solve_once(bool cx, bool unit, int64_t m, int64_t n, cplx al,
     void *ws = nullptr;
     HSMA_TRY(ws_alloc(&ws, blocked_workspace_bytes(cx, m, ib), s));
     hsma_status st = blocked_trsm(cx, unit, m, n, al, Ad, lda, Bd, ldb, ib, ws, s, mixed);
+    hsma_status st2 = ws_free(ws, s);
+    return st != HSMA_SUCCESS ? st : st2;
+}
+
+// One FP32 solve in place (STRSM, CTRSM): small kernel or blocked path.
+static hsma_status solve_once32(bool cx, bool unit, int64_t m, int64_t n, cplx al, const float *Ad,
+                                int64_t lda, float *Bd, int64_t ldb, int ib_override, int path,
+                                hipStream_t s, int *path_used, int *ib_used) {
+    if (al.re == 0.0 && al.im == 0.0) return launch_zero32(m, n, cx ? 2 : 1, Bd, ldb, s);
+    const bool small_ok = m <= 64;
+    const bool use_small = (path == 1) ? true : (path == 2 ? false : small_ok);
+    if (use_small) {
+        if (!small_ok) return HSMA_NOT_SUPPORTED;
+        if (path_used) *path_used = 1;
+        return launch_small_solve(cx, unit, (int)m, n, al, Ad, lda, Bd, ldb, s);
+    }
+    // The I_B table is the FP64 one of the same kind (real or complex).
+    int ib = ib_override > 0 ? ib_override : lookup_block_size(cx, m, n);
+    if (!valid_block_size(cx, ib)) return HSMA_INVALID_VALUE;
+    if (path_used) *path_used = 2;
+    if (ib_used) *ib_used = ib;
+    void *ws = nullptr;
+    HSMA_TRY(ws_alloc(&ws, blocked_workspace_bytes32(cx, m, ib), s));
+    hsma_status st = blocked_trsm32(cx, unit, m, n, al, Ad, lda, Bd, ldb, ib, ws, s);
     hsma_status st2 = ws_free(ws, s);
     return st != HSMA_SUCCESS ? st : st2;
 }
@@ -187,24 +230,31 @@ hsma_status trsm_impl(hsma_diag diag, int64_t m, int64_t n, const void *alpha, c
                       int path, hipStream_t s, int *path_used, int *ib_used,
                       const hsma_trsm_options *opt, hsma_trsm_report *rep) {
     bool quick = false;
-    HSMA_TRY(validate(diag, dtype, m, n, alpha, A, lda, B, ldb, &quick));
+    HSMA_TRY(validate(diag, dtype, m, n, alpha, A, lda, B, ldb, &quick, true));
     if (path_used) *path_used = 0;
     if (ib_used) *ib_used = 0;
-    const bool cx = dtype == HSMA_C64F;
+    const bool cx = is_complex(dtype);
+    const bool single = is_single(dtype);
     const bool mixed = opt && opt->precision == HSMA_PREC_MIXED;
     const int steps = opt ? opt->refine_steps : 0;
     const bool want_eta = opt && (opt->want_backward_error || opt->refine_steps < 0);
     if (mixed && cx) return HSMA_NOT_SUPPORTED;
+    // FP32 data: plain solves only (no mixed mode, refinement, backward
+    // error or graph replay).
+    if (single && (mixed || steps != 0 || want_eta || (opt && opt->use_graph)))
+        return HSMA_NOT_SUPPORTED;
     if (quick) {
         if (rep) rep->backward_error = want_eta ? 0.0 : -1.0;
         return HSMA_SUCCESS;
     }
     const bool unit = diag == HSMA_UNIT;
-    const double *a = static_cast<const double *>(alpha);
-    const cplx al{a[0], cx ? a[1] : 0.0};
+    const cplx al = read_alpha(dtype, alpha);
     DeviceInfo dev;
     HSMA_TRY(device_info(&dev));
     if (!dev.arch_ok) return HSMA_NOT_SUPPORTED;
+    if (single)
+        return solve_once32(cx, unit, m, n, al, static_cast<const float *>(A), lda,
+                            static_cast<float *>(B), ldb, ib_override, path, s, path_used, ib_used);
     double *Bd = static_cast<double *>(B);
     const double *Ad = static_cast<const double *>(A);
 
@@ -311,7 +361,7 @@ hsma_status hsma_trsm_ex(hsma_diag diag, int64_t m, int64_t n, const void *alpha
         if (o.reserved[i] != 0) return HSMA_INVALID_VALUE;
     if (o.use_graph != 0 && o.use_graph != 1) return HSMA_INVALID_VALUE;
     if (o.path < 0 || o.path > 2) return HSMA_INVALID_VALUE;
-    if (o.block_size != 0 && !hsma::valid_block_size(dtype == HSMA_C64F, o.block_size))
+    if (o.block_size != 0 && !hsma::valid_block_size(hsma::is_complex(dtype), o.block_size))
         return HSMA_INVALID_VALUE;
     if (o.precision != HSMA_PREC_FP64 && o.precision != HSMA_PREC_MIXED) return HSMA_INVALID_VALUE;
     if (o.refine_steps < -1 || o.refine_steps > 4) return HSMA_INVALID_VALUE;

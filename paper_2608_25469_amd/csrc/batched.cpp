@@ -20,8 +20,6 @@
 namespace hsma {
 
 // From api.cpp
-hsma_status validate(int diag, int dtype, int64_t m, int64_t n, const void *alpha, const void *A,
-                     int64_t lda, const void *B, int64_t ldb, bool *quick);
 hsma_status trsm_impl(hsma_diag diag, int64_t m, int64_t n, const void *alpha, const void *A,
                       int64_t lda, void *B, int64_t ldb, hsma_dtype dtype, int ib_override,
                       int path, hipStream_t s, int *path_used, int *ib_used,

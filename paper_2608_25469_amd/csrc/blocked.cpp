@@ -27,26 +27,30 @@ namespace hsma {
 
 namespace {
 
+// T is double (DTRSM, ZTRSM) or float (STRSM, CTRSM); complex data is
+// interleaved (re, im) of T, and every offset below counts components of T.
+template <typename T>
 struct Ctx {
     bool cx;
     bool unit;
-    bool mixed = false;  // trailing updates on the FP32 matrix cores
+    bool mixed = false;  // trailing updates on the FP32 matrix cores (double only)
     int64_t m, n;
     cplx alpha;
-    const double *A;
+    const T *A;
     int64_t lda;
-    double *B;
+    T *B;
     int64_t ldb;
     int ib;
-    double *W;  // nblk * ib * ib elements
-    double *T;  // combine scratch
+    T *W;  // nblk * ib * ib elements
+    T *Tm; // combine scratch
     hipStream_t s;
     int es() const { return cx ? 2 : 1; }
 };
 
 // Merge inverted diagonal sub-blocks of edge `sz` into blocks of edge 2*sz.
 // One batched launch pair per group of equally-sized pairs.
-hsma_status combine_group(const Ctx &c, int sz, int64_t first_row, int npairs_outer,
+template <typename T>
+hsma_status combine_group(const Ctx<T> &c, int sz, int64_t first_row, int npairs_outer,
                           int npairs_inner, int tsz) {
     // Pair (bo, bi): top-left at global row g = first_row + bo*ib + bi*2*sz,
     // top size sz, bottom size tsz (<= sz).
@@ -55,11 +59,11 @@ hsma_status combine_group(const Ctx &c, int sz, int64_t first_row, int npairs_ou
     const int64_t ib = c.ib, lda = c.lda;
     const int64_t blk0 = first_row / ib, off0 = first_row % ib;
     // A operand (C block of L): rows g+sz.., cols g..
-    const double *Lc = c.A + es * ((first_row + sz) + first_row * lda);
+    const T *Lc = c.A + es * ((first_row + sz) + first_row * lda);
     // inv(A) and inv(D) and W21 inside W.
-    const double *Wa = c.W + es * (blk0 * ib * ib + off0 + off0 * ib);
-    const double *Wd = c.W + es * (blk0 * ib * ib + (off0 + sz) + (off0 + sz) * ib);
-    double *W21 = c.W + es * (blk0 * ib * ib + (off0 + sz) + off0 * ib);
+    const T *Wa = c.W + es * (blk0 * ib * ib + off0 + off0 * ib);
+    const T *Wd = c.W + es * (blk0 * ib * ib + (off0 + sz) + (off0 + sz) * ib);
+    T *W21 = c.W + es * (blk0 * ib * ib + (off0 + sz) + off0 * ib);
     GemmBatch b1, b2;
     b1.count = b2.count = npairs_outer * npairs_inner;
     b1.inner = b2.inner = npairs_inner;
@@ -71,7 +75,7 @@ hsma_status combine_group(const Ctx &c, int sz, int64_t first_row, int npairs_ou
     b1.c_outer = es * (int64_t)npairs_inner * sz * sz;
     b1.c_inner = es * (int64_t)sz * sz;
     HSMA_TRY(launch_gemm(c.cx, GemmRole::Inverse, es * tsz, sz, es * sz, cplx{1.0, 0.0}, Lc, lda,
-                         Wa, es * ib, cplx{0.0, 0.0}, c.T, es * tsz, 0, b1, c.s));
+                         Wa, es * ib, cplx{0.0, 0.0}, c.Tm, es * tsz, 0, b1, c.s));
     // Step 2: W21 = -inv(D) * T   (tsz x sz) = (tsz x tsz)(tsz x sz)
     b2.a_outer = es * ib * ib;
     b2.a_inner = es * 2 * sz * (1 + ib);
@@ -80,11 +84,12 @@ hsma_status combine_group(const Ctx &c, int sz, int64_t first_row, int npairs_ou
     b2.c_outer = es * ib * ib;
     b2.c_inner = es * 2 * sz * (1 + ib);
     HSMA_TRY(launch_gemm(c.cx, GemmRole::Inverse, es * tsz, sz, es * tsz, cplx{-1.0, 0.0}, Wd, ib,
-                         c.T, es * tsz, cplx{0.0, 0.0}, W21, es * ib, 0, b2, c.s));
+                         c.Tm, es * tsz, cplx{0.0, 0.0}, W21, es * ib, 0, b2, c.s));
     return HSMA_SUCCESS;
 }
 
-hsma_status invert_diagonal(const Ctx &c, int base) {
+template <typename T>
+hsma_status invert_diagonal(const Ctx<T> &c, int base) {
     HSMA_TRY(launch_diag_inv_base(c.cx, c.unit, (int)c.m, base, c.ib, c.A, c.lda, c.W, c.s));
     const int64_t m = c.m, ib = c.ib;
     const int64_t nfull = m / ib;
@@ -104,19 +109,21 @@ hsma_status invert_diagonal(const Ctx &c, int base) {
     return HSMA_SUCCESS;
 }
 
-hsma_status leaf(const Ctx &c, int64_t blk, bool touched) {
+template <typename T>
+hsma_status leaf(const Ctx<T> &c, int64_t blk, bool touched) {
     const int es = c.es();
     const int64_t r0 = blk * c.ib;
     const int mr = (int)std::min<int64_t>(c.ib, c.m - r0);
-    const double *Wr = c.W + es * (blk * (int64_t)c.ib * c.ib);
-    double *Br = c.B + es * r0;
+    const T *Wr = c.W + es * (blk * (int64_t)c.ib * c.ib);
+    T *Br = c.B + es * r0;
     GemmBatch one;
     return launch_gemm(c.cx, GemmRole::Leaf, es * mr, (int)c.n, es * mr,
                        touched ? cplx{1.0, 0.0} : c.alpha, Wr, c.ib, Br, es * c.ldb,
                        cplx{0.0, 0.0}, Br, es * c.ldb, 0, one, c.s);
 }
 
-hsma_status update(const Ctx &c, int64_t r1, int64_t r2, int64_t k0, bool touched) {
+template <typename T>
+hsma_status update(const Ctx<T> &c, int64_t r1, int64_t r2, int64_t k0, bool touched) {
     // B[r1:r2] = beta B[r1:r2] - L[r1:r2, k0:r1] B[k0:r1]
     const int es = c.es();
     GemmBatch one;
@@ -127,7 +134,8 @@ hsma_status update(const Ctx &c, int64_t r1, int64_t r2, int64_t k0, bool touche
                        es * c.ldb, beta, c.B + es * r1, es * c.ldb, 0, one, c.s);
 }
 
-hsma_status recurse(const Ctx &c, int64_t b0, int64_t nb, bool touched) {
+template <typename T>
+hsma_status recurse(const Ctx<T> &c, int64_t b0, int64_t nb, bool touched) {
     if (nb == 1) return leaf(c, b0, touched);
     const int64_t h = nb / 2;
     HSMA_TRY(recurse(c, b0, h, touched));
@@ -137,22 +145,18 @@ hsma_status recurse(const Ctx &c, int64_t b0, int64_t nb, bool touched) {
     return recurse(c, b0 + h, nb - h, true);
 }
 
-}  // namespace
-
-size_t blocked_workspace_bytes(bool cx, int64_t m, int ib) {
+// Components of T the workspace needs: W (nblk blocks of ib x ib) and the
+// combine scratch (at most m/2 rows by ib/2 columns at the top level).
+size_t workspace_elems(bool cx, int64_t m, int ib) {
     const int64_t nblk = (m + ib - 1) / ib;
     const size_t es = cx ? 2 : 1;
-    const size_t w = (size_t)nblk * ib * ib * es * sizeof(double);
-    // Combine scratch: at most m/2 rows by ib/2 columns at the top level.
-    const size_t t = (size_t)((m + 1) / 2 + ib) * (size_t)ib * es * sizeof(double);
-    return w + t;
+    return (size_t)nblk * ib * ib * es + (size_t)((m + 1) / 2 + ib) * (size_t)ib * es;
 }
 
-// Enqueue the blocked solve.  `ws` must hold blocked_workspace_bytes().
-hsma_status blocked_trsm(bool cx, bool unit, int64_t m, int64_t n, cplx alpha, const double *A,
-                         int64_t lda, double *B, int64_t ldb, int ib, void *ws, hipStream_t s,
-                         bool mixed) {
-    Ctx c;
+template <typename T>
+hsma_status blocked_t(bool cx, bool unit, int64_t m, int64_t n, cplx alpha, const T *A,
+                      int64_t lda, T *B, int64_t ldb, int ib, void *ws, hipStream_t s, bool mixed) {
+    Ctx<T> c;
     c.mixed = mixed;
     c.cx = cx;
     c.unit = unit;
@@ -166,11 +170,34 @@ hsma_status blocked_trsm(bool cx, bool unit, int64_t m, int64_t n, cplx alpha, c
     c.ib = ib;
     c.s = s;
     const int64_t nblk = (m + ib - 1) / ib;
-    c.W = static_cast<double *>(ws);
-    c.T = c.W + (cx ? 2 : 1) * nblk * (int64_t)ib * ib;
+    c.W = static_cast<T *>(ws);
+    c.Tm = c.W + (cx ? 2 : 1) * nblk * (int64_t)ib * ib;
     const int base = std::min(ib, 64);
     HSMA_TRY(invert_diagonal(c, base));
     return recurse(c, 0, nblk, false);
+}
+
+}  // namespace
+
+size_t blocked_workspace_bytes(bool cx, int64_t m, int ib) {
+    return workspace_elems(cx, m, ib) * sizeof(double);
+}
+
+size_t blocked_workspace_bytes32(bool cx, int64_t m, int ib) {
+    return workspace_elems(cx, m, ib) * sizeof(float);
+}
+
+// Enqueue the blocked solve.  `ws` must hold blocked_workspace_bytes().
+hsma_status blocked_trsm(bool cx, bool unit, int64_t m, int64_t n, cplx alpha, const double *A,
+                         int64_t lda, double *B, int64_t ldb, int ib, void *ws, hipStream_t s,
+                         bool mixed) {
+    return blocked_t<double>(cx, unit, m, n, alpha, A, lda, B, ldb, ib, ws, s, mixed);
+}
+
+// The FP32 solve (STRSM, CTRSM).  `ws` must hold blocked_workspace_bytes32().
+hsma_status blocked_trsm32(bool cx, bool unit, int64_t m, int64_t n, cplx alpha, const float *A,
+                           int64_t lda, float *B, int64_t ldb, int ib, void *ws, hipStream_t s) {
+    return blocked_t<float>(cx, unit, m, n, alpha, A, lda, B, ldb, ib, ws, s, false);
 }
 
 // R <- R - tril(L) X, the residual of refinement and of the backward-error

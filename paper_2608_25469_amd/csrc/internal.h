@@ -82,6 +82,22 @@ hsma_status launch_small_solve(bool cplx_, bool unit, int m, int64_t n, cplx alp
                                const double *A, int64_t lda, double *B, int64_t ldb,
                                hipStream_t s);
 
+// The same on FP32 data (m <= 64).
+hsma_status launch_small_solve(bool cplx_, bool unit, int m, int64_t n, cplx alpha,
+                               const float *A, int64_t lda, float *B, int64_t ldb,
+                               hipStream_t s);
+
+// Argument checks of one problem (the documented order); FP32 data types
+// pass only with allow32, else HSMA_NOT_SUPPORTED.
+hsma_status validate(int diag, int dtype, int64_t m, int64_t n, const void *alpha, const void *A,
+                     int64_t lda, const void *B, int64_t ldb, bool *quick, bool allow32 = false);
+bool is_single(int dtype);
+bool is_complex(int dtype);
+cplx read_alpha(int dtype, const void *alpha);
+
+// B <- 0 on FP32 data (m x n, leading dimension ldb, `es` floats per element).
+hsma_status launch_zero32(int64_t m, int64_t n, int es, float *B, int64_t ldb, hipStream_t s);
+
 // B <- 0 (m x n, leading dimension ldb, `es` doubles per element).
 hsma_status launch_zero(int64_t m, int64_t n, int es, double *B, int64_t ldb, hipStream_t s);
 
@@ -126,6 +142,24 @@ int gemm_grouped_tile(GemmRole role, int max_m, int max_n, int *bm, int *bn);
 hsma_status launch_gemm_grouped(bool cplx_, GemmRole role, int bm, int bn, const GemmParams *descs,
                                 int nd, int64_t total_tiles, double flops, hipStream_t s);
 
+// Single-precision product (FP32 data, FP32 accumulation on the FP32 matrix
+// cores): the same roles, sizes and conventions as GemmParams.
+struct Gemm32Params {
+    int M, N, K;
+    const float *A;
+    int64_t lda;
+    const float *B;
+    int64_t ldb;
+    float *C;
+    int64_t ldc;
+    float alpha_re, alpha_im, beta_re, beta_im;
+    int tri_a;
+    int k_lower;
+    int inner;
+    int64_t a_outer, a_inner, b_outer, b_inner, c_outer, c_inner;
+    int tiles_m, tiles_n;
+};
+
 struct GemmBatch {
     int count = 1, inner = 1;
     int64_t a_outer = 0, a_inner = 0, b_outer = 0, b_inner = 0, c_outer = 0, c_inner = 0;
@@ -136,6 +170,11 @@ hsma_status launch_gemm(bool cplx_, GemmRole role, int M, int N, int K,
                         cplx alpha, const double *A, int64_t lda, const double *B,
                         int64_t ldb, cplx beta, double *C, int64_t ldc, int tri_a,
                         const GemmBatch &batch, hipStream_t s, int k_lower = 0);
+// The same product on FP32 data (FP32 matrix cores, FP32 accumulation).
+hsma_status launch_gemm(bool cplx_, GemmRole role, int M, int N, int K, cplx alpha,
+                        const float *A, int64_t lda, const float *B, int64_t ldb, cplx beta,
+                        float *C, int64_t ldc, int tri_a, const GemmBatch &batch, hipStream_t s,
+                        int k_lower = 0);
 
 // Inverse of every diagonal sub-block of edge `base` (<= 64) along the
 // diagonal of L (m rows, partitioned into consecutive chunks of `base`, last
@@ -144,6 +183,8 @@ hsma_status launch_gemm(bool cplx_, GemmRole role, int M, int N, int K,
 // Every element of W's ib x ib blocks not written by this call is zeroed.
 hsma_status launch_diag_inv_base(bool cplx_, bool unit, int m, int base, int ib,
                                  const double *A, int64_t lda, double *W, hipStream_t s);
+hsma_status launch_diag_inv_base(bool cplx_, bool unit, int m, int base, int ib,
+                                 const float *A, int64_t lda, float *W, hipStream_t s);
 
 // Synthetic serving inputs (Philox4x32-10, see hsma_generate_inputs).
 struct GenRequest {

@@ -26,8 +26,6 @@ hsma_status blocked_trsm(bool cx, bool unit, int64_t m, int64_t n, cplx alpha, c
                          int64_t lda, double *B, int64_t ldb, int ib, void *ws, hipStream_t s,
                          bool mixed);
 int lookup_block_size(bool cx, int64_t m, int64_t n);
-hsma_status validate(int diag, int dtype, int64_t m, int64_t n, const void *alpha, const void *A,
-                     int64_t lda, const void *B, int64_t ldb, bool *quick);
 
 namespace {
 

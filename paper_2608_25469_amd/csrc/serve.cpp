@@ -39,8 +39,6 @@ namespace hsma {
 
 size_t blocked_workspace_bytes(bool cx, int64_t m, int ib);
 int lookup_block_size(bool cx, int64_t m, int64_t n);
-hsma_status validate(int diag, int dtype, int64_t m, int64_t n, const void *alpha, const void *A,
-                     int64_t lda, const void *B, int64_t ldb, bool *quick);
 hsma_status trsm_batched_serial(const hsma_problem *probs, int64_t count, hipStream_t s);
 
 namespace {

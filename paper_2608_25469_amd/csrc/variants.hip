@@ -45,23 +45,23 @@ enum : int {
 
 constexpr int kT = 32;
 
-template <bool CX>
-struct Elem;
-template <>
-struct Elem<false> {
-    typedef double T;
-    static __device__ __forceinline__ T ld(const double *p, int64_t idx) { return p[idx]; }
-    static __device__ __forceinline__ void st(double *p, int64_t idx, T v, bool) { p[idx] = v; }
+// One element of the data: TC is the component type (double or float);
+// complex elements are (re, im) pairs moved as one access.
+template <typename TC, bool CX>
+struct Elem {
+    typedef TC T;
+    static __device__ __forceinline__ T ld(const TC *p, int64_t idx) { return p[idx]; }
+    static __device__ __forceinline__ void st(TC *p, int64_t idx, T v, bool) { p[idx] = v; }
 };
-template <>
-struct Elem<true> {
-    typedef dbl2u T;
-    static __device__ __forceinline__ T ld(const double *p, int64_t idx) {
-        return *reinterpret_cast<const dbl2u *>(p + 2 * idx);
+template <typename TC>
+struct Elem<TC, true> {
+    typedef TC T __attribute__((ext_vector_type(2), aligned(sizeof(TC))));
+    static __device__ __forceinline__ T ld(const TC *p, int64_t idx) {
+        return *reinterpret_cast<const T *>(p + 2 * idx);
     }
-    static __device__ __forceinline__ void st(double *p, int64_t idx, T v, bool conj) {
+    static __device__ __forceinline__ void st(TC *p, int64_t idx, T v, bool conj) {
         if (conj) v.y = -v.y;
-        *reinterpret_cast<dbl2u *>(p + 2 * idx) = v;
+        *reinterpret_cast<T *>(p + 2 * idx) = v;
     }
 };
 
@@ -69,11 +69,12 @@ struct Elem<true> {
 // src(i', j') or, with kSwap, src(j', i'), where i' and j' are i and j
 // reversed if asked.  Grid: one workgroup per 32 x 32 tile of dst, tiles
 // numbered down the columns of tiles (tr tile rows).
-template <bool CX>
-__global__ __launch_bounds__(256) void hsma_transform(const double *__restrict__ src, int64_t ldsrc,
-                                                      double *__restrict__ dst, int64_t ldd,
+template <typename TC, bool CX>
+__global__ __launch_bounds__(256) void hsma_transform(const TC *__restrict__ src, int64_t ldsrc,
+                                                      TC *__restrict__ dst, int64_t ldd,
                                                       int64_t R, int64_t C, int64_t tr, int flags) {
-    typedef typename Elem<CX>::T T;
+    typedef Elem<TC, CX> E;
+    typedef typename E::T T;
     __shared__ T tile[kT][kT + 1];
     const int64_t b = blockIdx.x;
     const int64_t i0 = (b % tr) * kT, j0 = (b / tr) * kT;
@@ -95,37 +96,38 @@ __global__ __launch_bounds__(256) void hsma_transform(const double *__restrict__
         for (int q = 0; q < kT / 8; ++q) {
             const int li = ty + 8 * q, lj = tx;
             const int64_t i = i0 + li, j = j0 + lj;
-            if (keep(i, j)) tile[li][lj] = Elem<CX>::ld(src, rj(j) + ri(i) * ldsrc);
+            if (keep(i, j)) tile[li][lj] = E::ld(src, rj(j) + ri(i) * ldsrc);
         }
         __syncthreads();
 #pragma unroll
         for (int q = 0; q < kT / 8; ++q) {
             const int lj = ty + 8 * q, li = tx;
             const int64_t i = i0 + li, j = j0 + lj;
-            if (keep(i, j)) Elem<CX>::st(dst, i + j * ldd, tile[li][lj], conj);
+            if (keep(i, j)) E::st(dst, i + j * ldd, tile[li][lj], conj);
         }
     } else {
 #pragma unroll
         for (int q = 0; q < kT / 8; ++q) {
             const int li = tx, lj = ty + 8 * q;
             const int64_t i = i0 + li, j = j0 + lj;
-            if (keep(i, j)) Elem<CX>::st(dst, i + j * ldd, Elem<CX>::ld(src, ri(i) + rj(j) * ldsrc), conj);
+            if (keep(i, j)) E::st(dst, i + j * ldd, E::ld(src, ri(i) + rj(j) * ldsrc), conj);
         }
     }
 }
 
-hsma_status launch_transform(bool cx, const double *src, int64_t ldsrc, double *dst, int64_t ldd,
+template <typename TC>
+hsma_status launch_transform(bool cx, const TC *src, int64_t ldsrc, TC *dst, int64_t ldd,
                              int64_t R, int64_t C, int flags, hipStream_t s) {
     if (R <= 0 || C <= 0) return HSMA_SUCCESS;
     const int64_t tr = (R + kT - 1) / kT, tc = (C + kT - 1) / kT;
     if (tr * tc > 0x7fffffff) return HSMA_INVALID_SIZE;
     ProfScope prof(HSMA_PHASE_OTHER, 0.0, s);
     if (cx)
-        hipLaunchKernelGGL(hsma_transform<true>, dim3((unsigned)(tr * tc)), dim3(256), 0, s, src,
-                           ldsrc, dst, ldd, R, C, tr, flags);
+        hipLaunchKernelGGL((hsma_transform<TC, true>), dim3((unsigned)(tr * tc)), dim3(256), 0, s,
+                           src, ldsrc, dst, ldd, R, C, tr, flags);
     else
-        hipLaunchKernelGGL(hsma_transform<false>, dim3((unsigned)(tr * tc)), dim3(256), 0, s, src,
-                           ldsrc, dst, ldd, R, C, tr, flags);
+        hipLaunchKernelGGL((hsma_transform<TC, false>), dim3((unsigned)(tr * tc)), dim3(256), 0, s,
+                           src, ldsrc, dst, ldd, R, C, tr, flags);
     HSMA_HIP(hipGetLastError());
     return HSMA_SUCCESS;
 }
@@ -159,6 +161,45 @@ GeneralPlan plan_general(int side, int uplo, int trans, bool cx, int64_t m, int6
     return g;
 }
 
+// The re-indexed solve of one general case on components TC.
+template <typename TC>
+hsma_status general_t(hsma_side side, hsma_uplo uplo, hsma_op trans, hsma_diag diag, int64_t m,
+                      int64_t n, const void *alpha, const TC *A, int64_t lda, TC *B, int64_t ldb,
+                      hsma_dtype dtype, hipStream_t s) {
+    const bool cx = is_complex(dtype);
+    const int es = cx ? 2 : 1;
+    const cplx al = read_alpha(dtype, alpha);
+    if (al.re == 0.0 && al.im == 0.0) {
+        if (is_single(dtype)) return launch_zero32(m, n, es, reinterpret_cast<float *>(B), ldb, s);
+        return launch_zero(m, n, es, reinterpret_cast<double *>(B), ldb, s);
+    }
+    const GeneralPlan g = plan_general(side, uplo, trans, cx, m, n);
+    const int64_t k = g.k, nr = g.nrhs;
+    const size_t a_elems = (size_t)k * k, b_elems = g.in_place ? 0 : (size_t)k * nr;
+    void *ws = nullptr;
+    HSMA_TRY(ws_alloc(&ws, (a_elems + b_elems) * es * sizeof(TC), s));
+    TC *Ap = static_cast<TC *>(ws);
+    TC *Bp = g.in_place ? B : Ap + es * a_elems;
+    const int64_t ldbp = g.in_place ? ldb : k;
+    const int rev = g.rev ? (kRevI | kRevJ) : 0;
+    const int fa = (diag == HSMA_UNIT ? kStrict : kLower) | rev | (g.swap_a ? kSwap : 0) |
+                   (g.conj_a ? kConj : 0);
+    hsma_status st = launch_transform<TC>(cx, A, lda, Ap, k, k, k, fa, s);
+    // B' = J B (left, reversed) or J B^T (right)
+    const bool left = side == HSMA_LEFT;
+    if (st == HSMA_SUCCESS && !g.in_place)
+        st = launch_transform<TC>(cx, B, ldb, Bp, k, k, nr, (g.rev ? kRevI : 0) | (left ? 0 : kSwap), s);
+    if (st == HSMA_SUCCESS)
+        st = trsm_impl(diag, k, nr, alpha, Ap, k, Bp, ldbp, dtype, 0, 0, s, nullptr, nullptr,
+                       nullptr, nullptr);
+    // B = J B' (left) or B(r, c) = B'(p(c), r) (right)
+    if (st == HSMA_SUCCESS && !g.in_place)
+        st = launch_transform<TC>(cx, Bp, k, B, ldb, m, n,
+                                  left ? (g.rev ? kRevI : 0) : (kSwap | (g.rev ? kRevJ : 0)), s);
+    hsma_status st2 = ws_free(ws, s);
+    return st != HSMA_SUCCESS ? st : st2;
+}
+
 }  // namespace hsma
 
 extern "C" hsma_status hsma_trsm_general(hsma_side side, hsma_uplo uplo, hsma_op trans,
@@ -168,16 +209,16 @@ extern "C" hsma_status hsma_trsm_general(hsma_side side, hsma_uplo uplo, hsma_op
     using namespace hsma;
     if ((side != HSMA_LEFT && side != HSMA_RIGHT) || (uplo != HSMA_LOWER && uplo != HSMA_UPPER) ||
         (trans != HSMA_OP_N && trans != HSMA_OP_T && trans != HSMA_OP_C) ||
-        (diag != HSMA_NON_UNIT && diag != HSMA_UNIT) || (dtype != HSMA_R64F && dtype != HSMA_C64F))
+        (diag != HSMA_NON_UNIT && diag != HSMA_UNIT) ||
+        (dtype != HSMA_R64F && dtype != HSMA_C64F && dtype != HSMA_R32F && dtype != HSMA_C32F))
         return HSMA_INVALID_VALUE;
     if (m < 0 || n < 0) return HSMA_INVALID_SIZE;
     const int64_t ka = side == HSMA_LEFT ? m : n;
     if (lda < std::max<int64_t>(1, ka) || ldb < std::max<int64_t>(1, m)) return HSMA_INVALID_SIZE;
     if (m == 0 || n == 0) return HSMA_SUCCESS;
     if (!alpha) return HSMA_INVALID_POINTER;
-    const bool cx = dtype == HSMA_C64F;
-    const double *a = static_cast<const double *>(alpha);
-    const bool azero = a[0] == 0.0 && (!cx || a[1] == 0.0);
+    const cplx al = read_alpha(dtype, alpha);
+    const bool azero = al.re == 0.0 && al.im == 0.0;
     if (!B || (!A && !azero)) return HSMA_INVALID_POINTER;
     if (m > (int64_t)1 << 30 || n > (int64_t)1 << 30) return HSMA_INVALID_SIZE;
     hipStream_t s = static_cast<hipStream_t>(stream);
@@ -187,34 +228,9 @@ extern "C" hsma_status hsma_trsm_general(hsma_side side, hsma_uplo uplo, hsma_op
     DeviceInfo dev;
     HSMA_TRY(device_info(&dev));
     if (!dev.arch_ok) return HSMA_NOT_SUPPORTED;
-    double *Bd = static_cast<double *>(B);
-    const int es = cx ? 2 : 1;
-    if (azero) return launch_zero(m, n, es, Bd, ldb, s);
-
-    const GeneralPlan g = plan_general(side, uplo, trans, cx, m, n);
-    const int64_t k = g.k, nr = g.nrhs;
-    const size_t a_elems = (size_t)k * k, b_elems = g.in_place ? 0 : (size_t)k * nr;
-    void *ws = nullptr;
-    HSMA_TRY(ws_alloc(&ws, (a_elems + b_elems) * es * sizeof(double), s));
-    double *Ap = static_cast<double *>(ws);
-    double *Bp = g.in_place ? Bd : Ap + es * a_elems;
-    const int64_t ldbp = g.in_place ? ldb : k;
-    const int rev = g.rev ? (kRevI | kRevJ) : 0;
-    int fa = (diag == HSMA_UNIT ? kStrict : kLower) | rev | (g.swap_a ? kSwap : 0) |
-             (g.conj_a ? kConj : 0);
-    hsma_status st = launch_transform(cx, static_cast<const double *>(A), lda, Ap, k, k, k, fa, s);
-    // B' = J B (left, reversed) or J B^T (right)
-    const bool left = side == HSMA_LEFT;
-    if (st == HSMA_SUCCESS && !g.in_place)
-        st = launch_transform(cx, Bd, ldb, Bp, k, k, nr,
-                              (g.rev ? kRevI : 0) | (left ? 0 : kSwap), s);
-    if (st == HSMA_SUCCESS)
-        st = trsm_impl(diag, k, nr, alpha, Ap, k, Bp, ldbp, dtype, 0, 0, s, nullptr, nullptr,
-                       nullptr, nullptr);
-    // B = J B' (left) or B(r, c) = B'(p(c), r) (right)
-    if (st == HSMA_SUCCESS && !g.in_place)
-        st = launch_transform(cx, Bp, k, Bd, ldb, m, n,
-                              left ? (g.rev ? kRevI : 0) : (kSwap | (g.rev ? kRevJ : 0)), s);
-    hsma_status st2 = ws_free(ws, s);
-    return st != HSMA_SUCCESS ? st : st2;
+    if (is_single(dtype))
+        return general_t<float>(side, uplo, trans, diag, m, n, alpha, static_cast<const float *>(A),
+                                lda, static_cast<float *>(B), ldb, dtype, s);
+    return general_t<double>(side, uplo, trans, diag, m, n, alpha, static_cast<const double *>(A),
+                             lda, static_cast<double *>(B), ldb, dtype, s);
 }

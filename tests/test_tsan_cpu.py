@@ -19,7 +19,8 @@ BUILD = os.path.join(ROOT, "paper_2608_25469_amd", "_build")
 HIPCC = "/opt/rocm/bin/hipcc"
 CLANG = "/opt/rocm/lib/llvm/bin/clang++"
 HOST_TUS = ["serve", "api", "alloc", "batched", "grouped", "blocked", "graph", "prof"]
-DEVICE_OBJS = ["gemm.hip.o", "gen.hip.o", "refine.hip.o", "small.hip.o", "small_d.hip.o", "small_z.hip.o"]
+# every translation unit with device code, from the regular build
+DEVICE_OBJS = sorted(os.path.basename(f) + ".o" for f in os.listdir(CSRC) if f.endswith(".hip"))
 
 pytestmark = pytest.mark.slow
 
