@@ -71,6 +71,10 @@ def _bind(lib):
     lib.oracle_backward_error_general.argtypes = [c_int, c_int, c_int, c_int, c_int, i64, i64, dp,
                                                   dp, i64, dp, i64, dp, i64, dp]
     lib.oracle_backward_error_general.restype = ctypes.c_double
+    for name in ("oracle_potrf_d", "oracle_potrf_z"):
+        f = getattr(lib, name)
+        f.argtypes = [i64, dp, i64]
+        f.restype = c_int
     lib.oracle_num_threads.argtypes = []
     lib.oracle_num_threads.restype = c_int
     lib.oracle_set_num_threads.argtypes = [c_int]
@@ -234,6 +238,27 @@ class OracleLib:
                                                  _ptr(R))
 
 
+    def potrf(self, A):
+        """Cholesky factor of a Hermitian positive definite A (lower triangle
+        read): returns (L, info) with L's strict upper triangle as given."""
+        L = np.array(A, dtype=A.dtype, order="F", copy=True)
+        n = L.shape[0]
+        if L.shape[1] < n:
+            raise ValueError("A must be n x n")
+        if L.dtype == np.float64:
+            info = self.lib.oracle_potrf_d(n, _ptr(L), _ld(L))
+        elif L.dtype == np.complex128:
+            info = self.lib.oracle_potrf_z(n, _ptr(L), _ld(L))
+        else:
+            raise TypeError("A must be float64 or complex128")
+        return L, int(info)
+
+    def cholesky_solve(self, L, B):
+        """X with L L^H X = B: L Y = B, then L^H X = Y (two triangular solves)."""
+        Y = self.solve(L, B, 1.0)
+        return self.solve_general(L, Y, 1.0, "L", "L", "C")
+
+
 SIDES = {"L": 0, "R": 1}
 UPLOS = {"L": 0, "U": 1}
 TRANS = {"N": 0, "T": 1, "C": 2}
@@ -264,6 +289,16 @@ def solve_general(A, B, alpha=1.0, side="L", uplo="L", trans="N", unit=False):
 def backward_error_general(A, X, B0, alpha=1.0, side="L", uplo="L", trans="N", unit=False):
     """Module-level :meth:`OracleLib.backward_error_general` on the default build."""
     return _load().backward_error_general(A, X, B0, alpha, side, uplo, trans, unit)
+
+
+def potrf(A):
+    """Module-level :meth:`OracleLib.potrf` on the default build."""
+    return _load().potrf(A)
+
+
+def cholesky_solve(L, B):
+    """Module-level :meth:`OracleLib.cholesky_solve` on the default build."""
+    return _load().cholesky_solve(L, B)
 
 
 def _load() -> OracleLib:

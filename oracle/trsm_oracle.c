@@ -586,6 +586,65 @@ double oracle_backward_error_general(int cx, int side, int uplo, int trans, int 
     return den > 0.0 ? rn / den : rn;
 }
 
+/* ------------------------------------------------------------------ */
+/* Cholesky factorization, the TRSM's first consumer (Sec. 1)           */
+/* ------------------------------------------------------------------ */
+/*
+ * A = L L^H for a real symmetric or complex Hermitian positive definite A
+ * (n x n, lda): L overwrites the lower triangle; the strict upper triangle is
+ * neither read nor written.  Column by column (left-looking):
+ *     l_jj = sqrt(a_jj - sum_{k<j} |l_jk|^2),
+ *     l_ij = (a_ij - sum_{k<j} l_ik conj(l_jk)) / l_jj   (i > j).
+ * Only the real part of a complex diagonal is used (a Hermitian matrix has a
+ * real diagonal).  Returns 0, or j + 1 when the pivot of column j is not
+ * positive (the factorization stops there, as LAPACK's potrf does).
+ */
+int oracle_potrf_d(int64_t n, double *A, int64_t lda)
+{
+    for (int64_t j = 0; j < n; ++j) {
+        double s = A[j + j * lda];
+        for (int64_t k = 0; k < j; ++k) s = s - A[j + k * lda] * A[j + k * lda];
+        if (!(s > 0.0)) return (int)(j + 1);
+        const double d = sqrt(s);
+        A[j + j * lda] = d;
+        for (int64_t i = j + 1; i < n; ++i) {
+            double t = A[i + j * lda];
+            for (int64_t k = 0; k < j; ++k) t = t - A[i + k * lda] * A[j + k * lda];
+            A[i + j * lda] = t / d;
+        }
+    }
+    return 0;
+}
+
+int oracle_potrf_z(int64_t n, double *A, int64_t lda)
+{
+    for (int64_t j = 0; j < n; ++j) {
+        double s = A[2 * (j + j * lda)];
+        for (int64_t k = 0; k < j; ++k) {
+            const double *l = A + 2 * (j + k * lda);
+            s = s - (l[0] * l[0] + l[1] * l[1]);
+        }
+        if (!(s > 0.0)) return (int)(j + 1);
+        const double d = sqrt(s);
+        A[2 * (j + j * lda)] = d;
+        A[2 * (j + j * lda) + 1] = 0.0;
+        for (int64_t i = j + 1; i < n; ++i) {
+            double tr = A[2 * (i + j * lda)], ti = A[2 * (i + j * lda) + 1];
+            for (int64_t k = 0; k < j; ++k) {
+                const double *a = A + 2 * (i + k * lda);   /* l_ik */
+                const double *b = A + 2 * (j + k * lda);   /* l_jk, conjugated */
+                double pr, pi;
+                z_mul(a[0], a[1], b[0], -b[1], &pr, &pi);
+                tr = tr - pr;
+                ti = ti - pi;
+            }
+            A[2 * (i + j * lda)] = tr / d;
+            A[2 * (i + j * lda) + 1] = ti / d;
+        }
+    }
+    return 0;
+}
+
 /* Threads the OpenMP loops above will use. */
 int oracle_num_threads(void)
 {

@@ -503,11 +503,76 @@ def pin_general_backward_error_checker(orc):
     assert abs(eta - np.sqrt(8.0) / 8.0) <= 1e-15, eta
 
 
+# ---------------------------------------------------------------------------
+# Cholesky factorization A = L L^H (the TRSM's consumer in the second
+# workload) and the solve L L^H X = B by two triangular solves.
+# ---------------------------------------------------------------------------
+def _integer_factor(rng, n, cx):
+    """Lower L with a power-of-two diagonal and small integer (Gaussian
+    integer) entries below it; A = L L^H is then exact, and so is every step
+    of the factorization of A (perfect-square pivots, divisions by powers
+    of two)."""
+    L = np.zeros((n, n), dtype=np.complex128 if cx else np.float64)
+    for j in range(n):
+        L[j, j] = float(rng.choice([1.0, 2.0, 4.0]))
+        for i in range(j + 1, n):
+            v = float(rng.integers(-2, 3))
+            L[i, j] = v + 1j * float(rng.integers(-2, 3)) if cx else v
+    A = L @ L.conj().T
+    return np.asfortranarray(L), np.asfortranarray(A)
+
+
+def pin_cholesky_exact(orc):
+    rng = np.random.default_rng(120)
+    for cx in (False, True):
+        for n in (1, 2, 7, 20):
+            L, A = _integer_factor(rng, n, cx)
+            Au = A.copy(order="F")
+            Au[np.triu_indices(n, 1)] = np.nan          # never read
+            got, info = orc.potrf(Au)
+            assert info == 0, ("cholesky info", cx, n, info)
+            assert _bits_equal(np.tril(got), L), ("cholesky exact", cx, n)
+            assert np.all(np.isnan(got[np.triu_indices(n, 1)])), ("upper touched", cx, n)
+
+
+def pin_cholesky_library(orc):
+    import scipy.linalg as sl
+    rng = np.random.default_rng(121)
+    for cx in (False, True):
+        for n in (5, 64, 150):
+            M = rng.standard_normal((n, n)) + (1j * rng.standard_normal((n, n)) if cx else 0)
+            A = np.asfortranarray(M @ M.conj().T + n * np.eye(n))
+            got, info = orc.potrf(A)
+            ref = sl.cholesky(A, lower=True)
+            assert info == 0
+            rel = np.linalg.norm(np.tril(got) - ref) / np.linalg.norm(ref)
+            assert rel <= 1e-13, ("cholesky scipy", cx, n, rel)
+            B = np.asfortranarray(rng.standard_normal((n, 3)) + (1j if cx else 0) * rng.standard_normal((n, 3)))
+            X = orc.cholesky_solve(np.asfortranarray(np.tril(got)), B)
+            Xr = np.linalg.solve(A, B)
+            rel = np.linalg.norm(X - Xr) / np.linalg.norm(Xr)
+            assert rel <= 1e-12, ("cholesky solve", cx, n, rel)
+
+
+def pin_cholesky_not_definite(orc):
+    """The first non-positive pivot stops the factorization with its
+    1-based column index."""
+    for cx in (False, True):
+        A = np.asfortranarray(np.diag([4.0, 9.0, 1.0, -1.0, 16.0]).astype(np.complex128 if cx else np.float64))
+        _, info = orc.potrf(A)
+        assert info == 4, ("not definite", cx, info)
+        A = np.asfortranarray(np.array([[1.0, 2.0], [2.0, 1.0]], dtype=np.complex128 if cx else np.float64))
+        _, info = orc.potrf(A)          # pivot 1 - 4 = -3 in column 2
+        assert info == 2, ("not definite 2x2", cx, info)
+
+
 # Cheap pins first: the mutant test stops at the first pin that fails.
 ALL_PINS = [
     pin_identity, pin_diagonal, pin_bidiagonal, pin_block_nilpotent,
     pin_integer_roundtrip, pin_alpha_zero, pin_backward_error_checker,
     pin_general_bidiagonal, pin_general_block_nilpotent, pin_general_consistency,
     pin_general_backward_error_checker, pin_general_bruteforce_rational,
+    pin_cholesky_exact, pin_cholesky_not_definite,
     pin_bruteforce_rational, pin_invariants, pin_library, pin_general_library,
+    pin_cholesky_library,
 ]

@@ -59,6 +59,17 @@ MUTATIONS = {
     "general_residual_right_index": ("OPEL(k, j, ar, ai);", "OPEL(j, k, ar, ai);"),
     "general_residual_conj": ("dot2_add_prod(&im, ai, xr);\n                }", "dot2_add_prod(&im, -ai, xr);\n                }"),
     "general_norm_of_op": ("s += cx ? hypot(ar, ai) : fabs(ar);", "s += cx ? hypot(ar, ai) : ar;"),
+    # the Cholesky factorization
+    "cholesky_pivot_sign": ("for (int64_t k = 0; k < j; ++k) s = s - A[j + k * lda] * A[j + k * lda];",
+                            "for (int64_t k = 0; k < j; ++k) s = s + A[j + k * lda] * A[j + k * lda];"),
+    "cholesky_row_index": ("for (int64_t k = 0; k < j; ++k) t = t - A[i + k * lda] * A[j + k * lda];",
+                           "for (int64_t k = 0; k < j; ++k) t = t - A[i + k * lda] * A[i + k * lda];"),
+    "cholesky_no_sqrt": ("const double d = sqrt(s);\n        A[j + j * lda] = d;",
+                         "const double d = s;\n        A[j + j * lda] = d;"),
+    "cholesky_conj_dropped": ("z_mul(a[0], a[1], b[0], -b[1], &pr, &pi);",
+                              "z_mul(a[0], a[1], b[0], b[1], &pr, &pi);"),
+    "cholesky_info_off_by_one": ("if (!(s > 0.0)) return (int)(j + 1);\n        const double d = sqrt(s);\n        A[j + j * lda] = d;\n        for",
+                                 "if (!(s > 0.0)) return (int)(j);\n        const double d = sqrt(s);\n        A[j + j * lda] = d;\n        for"),
 }
 
 
