@@ -174,6 +174,36 @@ hsma_status hsma_trsm_general(hsma_side side, hsma_uplo uplo, hsma_op trans, hsm
                               int64_t lda, void *B, int64_t ldb, hsma_dtype dtype,
                               hsma_stream_t stream);
 
+/* ------------------------------------------------------------------------ */
+/* Cholesky factorization and solve on the library's TRSM                    */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * hsma_potrf -- A = L L^H in place (the lower triangle of A is read and
+ * overwritten by L; the strict upper triangle is neither read nor written),
+ * for real symmetric (HSMA_R64F) or complex Hermitian (HSMA_C64F) positive
+ * definite A, n x n column-major with lda >= max(1, n).  TRSM is the core of
+ * this factorization (paper Sec. 1): recursion on halves, each step a
+ * right-side conjugate-transpose TRSM for the off-diagonal block
+ * (hsma_trsm_general) and a lower-triangular update on the FP64 matrix cores,
+ * diagonal blocks of <= 64 rows factored in LDS.  No definiteness check: a
+ * non-positive pivot gives NaN.  Workspace: about n^2/4 elements.
+ * Errors: bad dtype -> HSMA_INVALID_VALUE (FP32 -> HSMA_NOT_SUPPORTED);
+ * n < 0 or lda too small -> HSMA_INVALID_SIZE; n == 0 -> success; A NULL ->
+ * HSMA_INVALID_POINTER.  Asynchronous on `stream`.
+ */
+hsma_status hsma_potrf(int64_t n, void *A, int64_t lda, hsma_dtype dtype, hsma_stream_t stream);
+
+/*
+ * hsma_potrs -- solve A X = B with A = L L^H from hsma_potrf: L Y = B
+ * (hsma_trsm) then L^H X = Y (hsma_trsm_general); X overwrites B (n x nrhs,
+ * ldb >= max(1, n)).  L is read from the lower triangle of its array (lda).
+ * Errors as hsma_potrf, plus nrhs < 0 or ldb too small -> HSMA_INVALID_SIZE,
+ * B NULL -> HSMA_INVALID_POINTER.  Asynchronous on `stream`.
+ */
+hsma_status hsma_potrs(int64_t n, int64_t nrhs, const void *L, int64_t lda, void *B, int64_t ldb,
+                       hsma_dtype dtype, hsma_stream_t stream);
+
 /* Precision of the blocked path's trailing updates. */
 typedef enum {
     HSMA_PREC_FP64 = 0,   /* everything in FP64 (FP64 matrix cores) */
@@ -325,7 +355,9 @@ typedef enum {
     HSMA_PHASE_LEAF = 2,      /* diagonal solves X_r = alpha inv(D_r) B_r */
     HSMA_PHASE_SMALL = 3,     /* small-regime solves (m <= 64) */
     HSMA_PHASE_OTHER = 4,     /* zero fills, conversions, residuals, norms */
-    HSMA_PHASE_COUNT = 5
+    HSMA_PHASE_FACTOR = 5,    /* Cholesky diagonal blocks and trailing
+                                 Hermitian updates (hsma_potrf) */
+    HSMA_PHASE_COUNT = 6
 } hsma_phase;
 
 typedef struct {

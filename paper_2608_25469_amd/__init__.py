@@ -115,9 +115,9 @@ BACKEND_HIP, BACKEND_SIMULATED = 0, 1
 INPUT_DEVICE, INPUT_SYNTHETIC = 0, 1
 
 
-PHASE_DIAG_INV, PHASE_UPDATE, PHASE_LEAF, PHASE_SMALL, PHASE_OTHER = range(5)
-PHASE_COUNT = 5
-PHASE_NAMES = ["diag_inv", "update", "leaf_solve", "small", "other"]
+PHASE_DIAG_INV, PHASE_UPDATE, PHASE_LEAF, PHASE_SMALL, PHASE_OTHER, PHASE_FACTOR = range(6)
+PHASE_COUNT = 6
+PHASE_NAMES = ["diag_inv", "update", "leaf_solve", "small", "other", "factor"]
 
 _lib = None
 
@@ -137,6 +137,10 @@ def lib():
         L.hsma_trsm_ex.restype = i32
         L.hsma_trsm_general.argtypes = [i32, i32, i32, i32, i64, i64, vp, vp, i64, vp, i64, i32, vp]
         L.hsma_trsm_general.restype = i32
+        L.hsma_potrf.argtypes = [i64, vp, i64, i32, vp]
+        L.hsma_potrf.restype = i32
+        L.hsma_potrs.argtypes = [i64, i64, vp, i64, vp, i64, i32, vp]
+        L.hsma_potrs.restype = i32
         L.hsma_trsm_noalloc.argtypes = [i32, i64, i64, vp, vp, i64, vp, i64, i32, vp]
         L.hsma_trsm_noalloc.restype = i32
         L.hsma_noalloc_scratch_bytes.argtypes = []
@@ -345,6 +349,30 @@ def trsm_general(A, B, alpha=1.0, side: str = "L", uplo: str = "L", trans: str =
                                  ctypes.c_void_p(B.data_ptr()), leading_dim(B), code,
                                  ctypes.c_void_p(_stream_handle(stream)))
     _check(st, "hsma_trsm_general")
+    return B
+
+
+def potrf(A, stream=None):
+    """A = L L^H in place on the lower triangle of the square column-major
+    device tensor A (float64 or complex128)."""
+    code = _dtype_code(A)
+    n = A.shape[0]
+    if A.shape[1] != n:
+        raise ValueError("A must be square")
+    _check(lib().hsma_potrf(n, ctypes.c_void_p(A.data_ptr()), leading_dim(A), code,
+                            ctypes.c_void_p(_stream_handle(stream))), "hsma_potrf")
+    return A
+
+
+def potrs(L, B, stream=None):
+    """B <- X with L L^H X = B (L from potrf)."""
+    code = _dtype_code(B)
+    n, nrhs = B.shape
+    if L.dtype != B.dtype or L.shape[0] != n:
+        raise ValueError("L must be n x n of B's dtype")
+    _check(lib().hsma_potrs(n, nrhs, ctypes.c_void_p(L.data_ptr()), leading_dim(L),
+                            ctypes.c_void_p(B.data_ptr()), leading_dim(B), code,
+                            ctypes.c_void_p(_stream_handle(stream))), "hsma_potrs")
     return B
 
 

@@ -94,6 +94,9 @@ __device__ __forceinline__ void gemm_tile(const GemmParams &p, const GD *__restr
 
     const int m0 = tm * BM, n0 = tn * BN;
     const int M = p.M, N = p.N;
+    // Lower-triangular C (c_lower): a tile whose first column lies right of
+    // its last row (in elements: real-view rows / 2 for complex) is empty.
+    if (p.c_lower && n0 > (CX ? (m0 + BM - 1) / 2 : m0 + BM - 1)) return;
     // A lower-triangular A (k_lower) has nothing right of column m0 + BM - 1
     // in this tile's rows.
     const int K = (p.k_lower && m0 + BM < p.K) ? m0 + BM : p.K;
@@ -271,7 +274,7 @@ __device__ __forceinline__ void gemm_tile(const GemmParams &p, const GD *__restr
                     const double ar = v[2 * h], ai = v[2 * h + 1];
                     double r = p.alpha_re * ar - p.alpha_im * ai;
                     double q = p.alpha_re * ai + p.alpha_im * ar;
-                    if (row + 2 * h < M) {
+                    if (row + 2 * h < M && !(p.c_lower && col > (row + 2 * h) / 2)) {
                         if (!beta_zero) {
                             const double cr = dst[2 * h], ci = dst[2 * h + 1];
                             r += p.beta_re * cr - p.beta_im * ci;
@@ -284,7 +287,7 @@ __device__ __forceinline__ void gemm_tile(const GemmParams &p, const GD *__restr
             } else {
 #pragma unroll
                 for (int h = 0; h < 4; ++h) {
-                    if (row + h < M) {
+                    if (row + h < M && !(p.c_lower && col > row + h)) {
                         double r = p.alpha_re * v[h];
                         if (!beta_zero) r = __fma_rn(p.beta_re, dst[h], r);
                         dst[h] = r;
@@ -350,8 +353,10 @@ hsma_status launch_t(GemmParams p, int count, hipStream_t s) {
     const int phase = ROLE == (int)GemmRole::Update   ? HSMA_PHASE_UPDATE
                       : ROLE == (int)GemmRole::Leaf   ? HSMA_PHASE_LEAF
                       : ROLE == (int)GemmRole::Inverse ? HSMA_PHASE_DIAG_INV
+                      : ROLE == (int)GemmRole::Herk   ? HSMA_PHASE_FACTOR
                                                       : HSMA_PHASE_OTHER;
-    ProfScope prof(phase, 2.0 * p.M * (double)p.N * p.K * count, s);
+    // A lower-triangular C (Herk) computes about half of the product.
+    ProfScope prof(phase, (p.c_lower ? 1.0 : 2.0) * p.M * (double)p.N * p.K * count, s);
     hipLaunchKernelGGL((hsma_gemm<CX, BM, BN, WM, WN, ROLE>), dim3((unsigned)grid, count), dim3(256),
                        0, s, p);
     HSMA_HIP(hipGetLastError());
@@ -370,7 +375,7 @@ hsma_status launch_role(GemmParams p, int count, hipStream_t s) {
         return HSMA_NOT_SUPPORTED;
     }
     if (p.M <= 64 && p.N <= 64) return launch_t<CX, 64, 64, 2, 2, ROLE>(p, count, s);
-    if (ROLE == (int)GemmRole::Update) {
+    if (ROLE == (int)GemmRole::Update || ROLE == (int)GemmRole::Herk) {
         // The trailing updates of the deepest recursion levels are thin
         // (M = K = one or two block sizes): below HSMA_UPD_MIN_WG_PER_CU
         // workgroups per CU, narrower tiles keep every CU busy.
@@ -651,7 +656,7 @@ hsma_status launch_gemm_grouped(bool cplx_, GemmRole role, int bm, int bn, const
 hsma_status launch_gemm(bool cplx_, GemmRole role, int M, int N, int K, cplx alpha,
                         const double *A, int64_t lda, const double *B, int64_t ldb, cplx beta,
                         double *C, int64_t ldc, int tri_a, const GemmBatch &batch,
-                        hipStream_t s, int k_lower) {
+                        hipStream_t s, int k_lower, int c_lower) {
     if (M <= 0 || N <= 0 || batch.count <= 0) return HSMA_SUCCESS;
     GemmParams p{};
     p.M = M;
@@ -669,6 +674,7 @@ hsma_status launch_gemm(bool cplx_, GemmRole role, int M, int N, int K, cplx alp
     p.beta_im = beta.im;
     p.tri_a = tri_a;
     p.k_lower = (k_lower && tri_a) ? 1 : 0;
+    p.c_lower = c_lower ? 1 : 0;
     p.inner = batch.inner > 0 ? batch.inner : 1;
     p.a_outer = batch.a_outer;
     p.a_inner = batch.a_inner;
@@ -690,6 +696,8 @@ hsma_status launch_gemm(bool cplx_, GemmRole role, int M, int N, int K, cplx alp
             return cplx_ ? launch_role<true, 2>(p, batch.count, s) : launch_role<false, 2>(p, batch.count, s);
         case GemmRole::Residual:
             return cplx_ ? launch_role<true, 3>(p, batch.count, s) : launch_role<false, 3>(p, batch.count, s);
+        case GemmRole::Herk:
+            return cplx_ ? launch_role<true, 5>(p, batch.count, s) : launch_role<false, 5>(p, batch.count, s);
         default:
             break;
     }

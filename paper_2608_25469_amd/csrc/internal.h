@@ -110,7 +110,7 @@ hsma_status launch_zero(int64_t m, int64_t n, int es, double *B, int64_t ldb, hi
 // (b / inner) * s_outer + (b % inner) * s_inner (in doubles) for each operand.
 // tri_a: A is the m x m diagonal block of a lower-triangular matrix, read only
 // on and below its diagonal (0: plain, 1: lower non-unit, 2: lower unit).
-enum class GemmRole { Update = 0, Leaf = 1, Inverse = 2, Residual = 3, UpdateMixed = 4 };
+enum class GemmRole { Update = 0, Leaf = 1, Inverse = 2, Residual = 3, UpdateMixed = 4, Herk = 5 };
 
 // Parameters of one product (also the descriptor of a grouped launch, read
 // by the kernel from device memory).
@@ -130,6 +130,8 @@ struct GemmParams {
     int tile0;            // grouped launch: first tile of this product in the grid
     int k_lower;          // 1: A is lower triangular as a whole (with tri_a), so a
                           // tile of rows [m0, m0 + BM) stops its K loop at m0 + BM
+    int c_lower;          // 1: only the lower triangle of C (column <= row, in
+                          // elements) is computed and stored
 };
 
 // Tile shape a grouped launch of `role` uses when its largest product has
@@ -166,10 +168,13 @@ struct GemmBatch {
 };
 // k_lower = 1: A (with tri_a != 0) is a whole lower-triangular matrix, so
 // each row tile reads only the columns left of its last row.
+// c_lower = 1: only C's lower triangle (element column <= element row) is
+// written; tiles wholly above the diagonal do nothing.
 hsma_status launch_gemm(bool cplx_, GemmRole role, int M, int N, int K,
                         cplx alpha, const double *A, int64_t lda, const double *B,
                         int64_t ldb, cplx beta, double *C, int64_t ldc, int tri_a,
-                        const GemmBatch &batch, hipStream_t s, int k_lower = 0);
+                        const GemmBatch &batch, hipStream_t s, int k_lower = 0,
+                        int c_lower = 0);
 // The same product on FP32 data (FP32 matrix cores, FP32 accumulation).
 hsma_status launch_gemm(bool cplx_, GemmRole role, int M, int N, int K, cplx alpha,
                         const float *A, int64_t lda, const float *B, int64_t ldb, cplx beta,
@@ -185,6 +190,10 @@ hsma_status launch_diag_inv_base(bool cplx_, bool unit, int m, int base, int ib,
                                  const double *A, int64_t lda, double *W, hipStream_t s);
 hsma_status launch_diag_inv_base(bool cplx_, bool unit, int m, int base, int ib,
                                  const float *A, int64_t lda, float *W, hipStream_t s);
+
+// dst (R x C, ldd) = src^H for src C x R (ldsrc); the transpose for real data.
+hsma_status launch_conj_transpose(bool cx, const double *src, int64_t ldsrc, double *dst,
+                                  int64_t ldd, int64_t R, int64_t C, hipStream_t s);
 
 // Synthetic serving inputs (Philox4x32-10, see hsma_generate_inputs).
 struct GenRequest {

@@ -134,6 +134,13 @@ hsma_status launch_transform(bool cx, const TC *src, int64_t ldsrc, TC *dst, int
 
 }  // namespace
 
+// dst (R x C, ldd) = src^H, src being C x R (ldsrc); the transpose for real
+// data.
+hsma_status launch_conj_transpose(bool cx, const double *src, int64_t ldsrc, double *dst,
+                                  int64_t ldd, int64_t R, int64_t C, hipStream_t s) {
+    return launch_transform<double>(cx, src, ldsrc, dst, ldd, R, C, kSwap | kConj, s);
+}
+
 // How a general case maps onto the left-lower solve (host only).
 struct GeneralPlan {
     int64_t k;        // order of the effective operator
