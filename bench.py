@@ -69,7 +69,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="default",
                     choices=["default", "large_real", "large_complex", "large_real_fp32",
-                             "large_complex_fp32", "batched", "single", "mixed", "serving", "variants"])
+                             "large_complex_fp32", "batched", "single", "mixed", "serving", "variants",
+                             "cholesky"])
     ap.add_argument("--ib", type=int, default=0, help="force I_B (0 = tuning table)")
     ap.add_argument("--m", type=int, default=0, help="override m (and n) for sweeps")
     ap.add_argument("--n", type=int, default=0)
@@ -530,6 +531,88 @@ def run_variants(args, torch, hs, k=8192, reps=3):
             "flops_per_solve": fl, "rows": rows}
 
 
+def hermitian_pd(n, cx, seed):
+    """A = (R + R^H)/2 + n I, R with entries U(-1, 1) (complex: real and
+    imaginary parts): Hermitian, eigenvalues within n +- 2 sqrt(n), so
+    positive definite and well conditioned; O(n^2) to draw."""
+    rng = np.random.default_rng(seed)
+    R = rng.uniform(-1.0, 1.0, size=(n, n))
+    if cx:
+        R = R + 1j * rng.uniform(-1.0, 1.0, size=(n, n))
+    A = (R + R.conj().T) * 0.5
+    A[np.diag_indices(n)] += n
+    return np.asfortranarray(A)
+
+
+def run_cholesky(args, torch, hs, sizes=((16384, False), (8192, True)), reps=3):
+    """Cholesky factorization on the library's TRSM (hsma_potrf) against
+    rocSOLVER's potrf on the same GPU; flops n^3/3 (complex 4 n^3/3).  The
+    factor is checked by its reconstruction residual on sampled columns."""
+    rows = []
+    for n, cx in sizes:
+        A = hermitian_pd(n, cx, 5)
+        Ad0 = hs.to_colmajor(A)
+        Ad = hs.colmajor(n, n, Ad0.dtype)
+        fl = (4.0 if cx else 1.0) * n ** 3 / 3.0
+        Ad.copy_(Ad0)
+        hs.potrf(Ad)
+        torch.cuda.synchronize()
+        cols = np.unique(np.linspace(0, n - 1, num=8).astype(int))
+        Lh = np.tril(Ad.cpu().numpy())          # (n, n) host copy (logical order), lower part
+        res = 0.0
+        for j in cols:
+            col = Lh @ np.conj(Lh[j, :])          # (L L^H)[:, j]
+            res = max(res, np.max(np.abs(col - A[:, j])) / np.max(np.abs(A)))
+        del Lh
+        ts = []
+        hs.profile_begin()
+        for _ in range(reps):
+            Ad.copy_(Ad0)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            hs.potrf(Ad)
+            torch.cuda.synchronize()
+            ts.append((time.perf_counter() - t) * 1e3)
+        prof = hs.profile_end()
+        busy = sum(v["ms"] for v in prof.values())
+        ms = min(ts)
+        trsm_ms = sum(prof[k]["ms"] for k in ("diag_inv", "update", "leaf_solve", "small", "other")) / reps
+        row = {"workload": f"{'ZPOTRF' if cx else 'DPOTRF'} n={n}, A = (R + R^H)/2 + n I, seed 5",
+               "ms": round(ms, 3), "gflops": round(fl / (ms * 1e-3) / 1e9, 1),
+               "trsm_share": round(trsm_ms * reps / busy, 4) if busy else None,
+               "factor_share": round(prof["factor"]["ms"] / busy, 4) if busy else None,
+               "reconstruction_residual_sampled": res, "parity_ok": bool(res <= 10 * n * 2.0 ** -53)}
+        try:
+            lib = ctypes.CDLL("librocsolver.so")
+            rb = RocBlas(torch.cuda.current_stream().cuda_stream)
+            f = lib.rocsolver_zpotrf if cx else lib.rocsolver_dpotrf
+            f.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,
+                          ctypes.c_int32, ctypes.c_void_p]
+            f.restype = ctypes.c_int32
+            info = torch.zeros(1, dtype=torch.int32, device="cuda")
+            rts = []
+            for _ in range(reps):
+                Ad.copy_(Ad0)
+                torch.cuda.synchronize()
+                t = time.perf_counter()
+                st = f(rb.h, 122, n, ctypes.c_void_p(Ad.data_ptr()), hs.leading_dim(Ad),
+                       ctypes.c_void_p(info.data_ptr()))
+                torch.cuda.synchronize()
+                rts.append((time.perf_counter() - t) * 1e3)
+                if st != 0:
+                    raise RuntimeError(f"rocsolver potrf: {st}")
+            row["rocsolver_ms"] = round(min(rts), 3)
+            row["speedup_over_rocsolver"] = round(min(rts) / ms, 3)
+        except Exception as e:  # reported, not fatal
+            row["rocsolver"] = {"error": repr(e)}
+        rows.append(row)
+        log(f"potrf n={n} complex={cx}: {ms:.2f} ms ({row['gflops']} GF/s), rocSOLVER {row.get('rocsolver_ms')} ms, "
+            f"TRSM share {row['trsm_share']}, residual {res:.1e}")
+        del Ad, Ad0
+        torch.cuda.empty_cache()
+    return {"rows": rows, "flop_convention": "n^3/3 (complex 4 n^3/3)"}
+
+
 def run_graph(args, torch, hs, sizes=(256, 512, 1024), reps=30):
     """Blocked schedule replayed as a captured HIP graph vs launched eagerly,
     on mid-size DTRSMs where launch overhead matters (same inputs, results
@@ -825,6 +908,12 @@ def run_headline(args, torch, hs, names):
     torch.cuda.empty_cache()
     hs.workspace_release()
     try:
+        out["cholesky"] = run_cholesky(sub, torch, hs)
+    except Exception as e:
+        out["cholesky"] = {"error": repr(e)}
+    torch.cuda.empty_cache()
+    hs.workspace_release()
+    try:
         out["graph"] = run_graph(sub, torch, hs)
     except Exception as e:
         out["graph"] = {"error": repr(e)}
@@ -889,6 +978,13 @@ def main():
         res = run_serving(args, torch, hs)
         workload = (f"TRSM serving: Poisson {args.rate:.0f} req/s for {args.duration:.0f} s, m log-U[8,4096], "
                     f"n log-U[1,512], 70% real / 30% complex, seed 4")
+    elif args.workload == "cholesky":
+        r = run_cholesky(args, torch, hs)
+        first = r["rows"][0]
+        res = {"value": first["gflops"], "unit": "GFLOP/s", "ms_per_step": first["ms"], "dtype": "f64",
+               "pct_fp64_peak": round(100 * first["gflops"] / (FP64_PEAK_TFLOPS * 1e3), 2),
+               "extra_config": {}, "cholesky": r}
+        workload = first["workload"]
     elif args.workload == "variants":
         r = run_variants(args, torch, hs, k=args.m or 8192)
         first = r["rows"][0]
@@ -920,7 +1016,7 @@ def main():
                         "flop_convention": "real m^2 n; complex 4 m^2 n + 2 m n"}, **res["extra_config"]),
     }
     for k in ("solves_per_s", "gflops", "phases", "parity", "roofline", "rocblas", "cpu_baseline",
-              "mixed", "serving", "variants"):
+              "mixed", "serving", "variants", "cholesky"):
         if k in res:
             out[k] = res[k]
     if headline is not None:

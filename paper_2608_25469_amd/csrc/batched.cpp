@@ -51,10 +51,12 @@ constexpr int kForkStreams = 8;
 // 64-row instance: its left-looking walk skips the 16-row blocks past each
 // item's m, so the work still follows m, and one launch keeps the whole GPU
 // on one longest-first queue instead of several launches competing for it.
-int group_of(bool cx, bool unit, int m) {
-    (void)m;
-    return ((cx ? 1 : 0) * 2 + (unit ? 1 : 0)) * 8 + 7;
+// Problems with m, n <= HSMA_TINY_MAX form their own group (slot 0 of the
+// pair), solved four per workgroup by the fused kernel.
+int group_of(bool cx, bool unit, int m, int64_t n) {
+    return ((cx ? 1 : 0) * 2 + (unit ? 1 : 0)) * 8 + (tiny_fits(m, n) ? 0 : 7);
 }
+bool group_is_tiny(int g) { return g % 8 == 0; }
 
 struct DevicePool {
     bool init = false;
@@ -131,7 +133,7 @@ static void build_image(const hsma_problem *probs, int64_t count, BatchTable *t,
             continue;
         }
         const bool cx = p.dtype == HSMA_C64F, unit = p.diag == HSMA_UNIT;
-        const int g = group_of(cx, unit, (int)p.m);
+        const int g = group_of(cx, unit, (int)p.m, p.n);
         const int es = cx ? 2 : 1;
         for (int64_t c0 = 0; c0 < p.n; c0 += 64) {
             Item it;
@@ -211,8 +213,11 @@ static hsma_status run_table(const BatchTable &t, hipStream_t s, bool fork = tru
             const void *items = base + (size_t)t.start[g] * sizeof(Item);
             {
                 ProfScope prof(HSMA_PHASE_SMALL, 0.0, fs);
-                st = cx ? launch_small_group_z(unit, nch, items, t.count[g], fs)
-                        : launch_small_group_d(unit, nch, items, t.count[g], fs);
+                if (group_is_tiny(g))
+                    st = launch_tiny_group(cx, unit, items, t.count[g], fs);
+                else
+                    st = cx ? launch_small_group_z(unit, nch, items, t.count[g], fs)
+                            : launch_small_group_d(unit, nch, items, t.count[g], fs);
             }
             if (fs != s) {
                 hipEvent_t j;
@@ -302,7 +307,7 @@ static hsma_status upload(const std::vector<unsigned char> &img, void *dev, hipS
 hsma_status trsm_batched_serial(const hsma_problem *probs, int64_t count, hipStream_t s) {
     HSMA_TRY(check_all(probs, count, nullptr));
     if (count == 0) return HSMA_SUCCESS;
-    if (small_item_bytes_d() != sizeof(Item)) return HSMA_NOT_SUPPORTED;
+    if (small_item_bytes_d() != sizeof(Item) || tiny_item_bytes() != sizeof(Item)) return HSMA_NOT_SUPPORTED;
     BatchTable t;
     std::vector<unsigned char> img;
     build_image(probs, count, &t, &img);
@@ -331,7 +336,7 @@ hsma_status hsma_trsm_batched(const hsma_problem *probs, int64_t count, int64_t 
     using namespace hsma;
     HSMA_TRY(check_all(probs, count, first_bad));
     if (count == 0) return HSMA_SUCCESS;
-    if (small_item_bytes_d() != sizeof(Item)) return HSMA_NOT_SUPPORTED;
+    if (small_item_bytes_d() != sizeof(Item) || tiny_item_bytes() != sizeof(Item)) return HSMA_NOT_SUPPORTED;
     hipStream_t s = static_cast<hipStream_t>(stream);
     BatchTable t;
     std::vector<unsigned char> img;
@@ -353,7 +358,7 @@ hsma_status hsma_batch_plan_create(const hsma_problem *probs, int64_t count, int
     if (!plan) return HSMA_INVALID_POINTER;
     *plan = nullptr;
     HSMA_TRY(check_all(probs, count, first_bad));
-    if (small_item_bytes_d() != sizeof(Item)) return HSMA_NOT_SUPPORTED;
+    if (small_item_bytes_d() != sizeof(Item) || tiny_item_bytes() != sizeof(Item)) return HSMA_NOT_SUPPORTED;
     hsma_batch_plan *p = new hsma_batch_plan();
     std::vector<unsigned char> img;
     build_image(probs, count, &p->table, &img);

@@ -8,6 +8,12 @@
 
 #include "../../include/hsma.h"
 
+// Problems with m, n <= HSMA_TINY_MAX take the fused four-per-wavefront
+// kernel (tiny.hip), alone and in batches.
+#ifndef HSMA_TINY_MAX
+#define HSMA_TINY_MAX 16
+#endif
+
 // Size of the allocation-free entry point's per-device scratch array.
 #define HSMA_NOALLOC_SCRATCH_BYTES (64ull << 20)
 
@@ -81,6 +87,14 @@ size_t ws_cached_bytes();
 hsma_status launch_small_solve(bool cplx_, bool unit, int m, int64_t n, cplx alpha,
                                const double *A, int64_t lda, double *B, int64_t ldb,
                                hipStream_t s);
+
+// Fused very small solves (m, n <= HSMA_TINY_MAX): one problem, or a device
+// table of items in the batched layout, four per workgroup.
+bool tiny_fits(int64_t m, int64_t n);
+size_t tiny_item_bytes();
+hsma_status launch_tiny_one(bool cx, bool unit, int m, int n, cplx alpha, const double *A,
+                            int64_t lda, double *B, int64_t ldb, hipStream_t s);
+hsma_status launch_tiny_group(bool cx, bool unit, const void *items, int count, hipStream_t s);
 
 // The same on FP32 data (m <= 64).
 hsma_status launch_small_solve(bool cplx_, bool unit, int m, int64_t n, cplx alpha,

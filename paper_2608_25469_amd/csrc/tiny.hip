@@ -1,0 +1,164 @@
+// Fused solves of very small problems (m, n <= 16): four problems per
+// wavefront.  The paper names kernel fusion for very small scales as future
+// work (Sec. 6).
+//
+// The small-solve kernel gives each problem a whole 64-lane wavefront (lane =
+// column) and stages L in 16-row blocks; a problem with n <= 16 then leaves
+// at least 48 lanes idle and m <= 16 uses a single, mostly empty block.  Here
+// each 16-lane quarter of the wavefront is one problem: its lower triangle
+// (<= 16 x 16) sits in the quarter's own LDS region, lane j of the quarter
+// holds column j in 16 registers, and the substitution chain
+//     x_k <- x_k / l_kk,   x_i <- x_i - l_ik x_k  (i > k)
+// runs over the problem's own m.  The lanes of a quarter read the same l_ik
+// (an LDS broadcast); the four quarters' regions are offset so that their
+// four addresses fall in different banks.  Rows beyond m are zero in LDS and
+// in registers.  The per-problem arithmetic does not depend on which quarter
+// or launch a problem lands in, so a problem gives the same bits alone and
+// in a batch.
+
+#include "internal.h"
+
+namespace hsma {
+namespace {
+
+// Same layout as the batched item of the small-solve kernel.
+struct TinyItem {
+    const double *A;
+    double *B;
+    int64_t lda, ldb;
+    int32_t m, ncols;
+    double ar, ai;
+};
+
+constexpr int kMax = 16;
+// Quarter stride in elements: 16 x 17 plus padding that puts the four
+// quarters' copies of one element in different LDS banks.
+template <bool CX>
+constexpr int quarter_stride() { return CX ? 276 : 280; }
+
+template <bool CX>
+struct D;
+template <>
+struct D<false> {
+    typedef double V;
+    static __device__ __forceinline__ V ld(const double *p, int64_t i) { return p[i]; }
+    static __device__ __forceinline__ void st(double *p, int64_t i, V v) { p[i] = v; }
+    static __device__ __forceinline__ V zero() { return 0.0; }
+    static __device__ __forceinline__ V one() { return 1.0; }
+    static __device__ __forceinline__ V mul(V a, V b) { return a * b; }
+    static __device__ __forceinline__ V fnms(V acc, V a, V b) { return acc - a * b; }
+    static __device__ __forceinline__ V div(V a, V d) { return a / d; }
+    static __device__ __forceinline__ V make(double r, double) { return r; }
+};
+template <>
+struct D<true> {
+    typedef dbl2u V;
+    static __device__ __forceinline__ V ld(const double *p, int64_t i) {
+        return *reinterpret_cast<const dbl2u *>(p + 2 * i);
+    }
+    static __device__ __forceinline__ void st(double *p, int64_t i, V v) {
+        *reinterpret_cast<dbl2u *>(p + 2 * i) = v;
+    }
+    static __device__ __forceinline__ V zero() { return V{0.0, 0.0}; }
+    static __device__ __forceinline__ V one() { return V{1.0, 0.0}; }
+    static __device__ __forceinline__ V mul(V a, V b) {
+        return V{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+    }
+    static __device__ __forceinline__ V fnms(V acc, V a, V b) {
+        return V{acc.x - (a.x * b.x - a.y * b.y), acc.y - (a.x * b.y + a.y * b.x)};
+    }
+    static __device__ __forceinline__ V div(V a, V d) {  // a conj(d) / |d|^2
+        const double den = d.x * d.x + d.y * d.y;
+        return V{(a.x * d.x + a.y * d.y) / den, (a.y * d.x - a.x * d.y) / den};
+    }
+    static __device__ __forceinline__ V make(double r, double i) { return V{r, i}; }
+};
+
+// Workgroup b solves items 4b .. 4b + 3 (those below count); with items ==
+// nullptr it solves `one` alone (a single call, no descriptor upload).
+template <bool CX, bool UNIT>
+__global__ __launch_bounds__(64) void hsma_tiny(TinyItem one, const TinyItem *__restrict__ items,
+                                                int count) {
+    typedef D<CX> O;
+    typedef typename O::V V;
+    constexpr int QS = quarter_stride<CX>();
+    __shared__ V Ls[4 * QS];
+    const int q = threadIdx.x >> 4, lane = threadIdx.x & 15;
+    const int idx = blockIdx.x * 4 + q;
+    const bool active = items ? idx < count : q == 0;
+    TinyItem it = one;
+    if (items && active) it = items[idx];
+    V *L = Ls + q * QS;
+    // alpha == 0: B <- 0, and neither A nor B is read (A may be null).
+    const bool azero = it.ar == 0.0 && (!CX || it.ai == 0.0);
+    const int m = (active && !azero) ? it.m : 0;
+    const double *A = (const double *)(const HSMA_GLOBAL double *)it.A;
+    // Stage the quarter's lower triangle (16 x 16, ld 17); zero elsewhere.
+    for (int e = lane; e < kMax * kMax; e += 16) {
+        const int i = e % kMax, k = e / kMax;
+        V v = O::zero();
+        if (i < m && k < m) {
+            if (k < i) v = O::ld(A, i + (int64_t)k * it.lda);
+            else if (k == i) v = UNIT ? O::one() : O::ld(A, i + (int64_t)k * it.lda);
+        } else if (i == k) {
+            v = O::one();
+        }
+        L[i + k * (kMax + 1)] = v;
+    }
+    __syncthreads();
+    if (!active || lane >= it.ncols) return;
+    double *col = (double *)(HSMA_GLOBAL double *)it.B + (CX ? 2 : 1) * (int64_t)lane * it.ldb;
+    if (azero) {
+        for (int i = 0; i < it.m; ++i) O::st(col, i, O::zero());
+        return;
+    }
+    const V alpha = O::make(it.ar, it.ai);
+    V x[kMax];
+#pragma unroll
+    for (int i = 0; i < kMax; ++i) x[i] = i < m ? O::mul(alpha, O::ld(col, i)) : O::zero();
+#pragma unroll
+    for (int k = 0; k < kMax; ++k) {
+        if (k < m) {
+            if (!UNIT) x[k] = O::div(x[k], L[k + k * (kMax + 1)]);
+            const V xk = x[k];
+#pragma unroll
+            for (int i = k + 1; i < kMax; ++i) x[i] = O::fnms(x[i], L[i + k * (kMax + 1)], xk);
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < kMax; ++i)
+        if (i < m) O::st(col, i, x[i]);
+}
+
+template <bool CX>
+hsma_status tiny_t(bool unit, const TinyItem &one, const TinyItem *items, int count, hipStream_t s) {
+    const unsigned wgs = items ? (unsigned)((count + 3) / 4) : 1u;
+    if (unit) hipLaunchKernelGGL((hsma_tiny<CX, true>), dim3(wgs), dim3(64), 0, s, one, items, count);
+    else hipLaunchKernelGGL((hsma_tiny<CX, false>), dim3(wgs), dim3(64), 0, s, one, items, count);
+    HSMA_HIP(hipGetLastError());
+    return HSMA_SUCCESS;
+}
+
+}  // namespace
+
+bool tiny_fits(int64_t m, int64_t n) { return m >= 1 && m <= HSMA_TINY_MAX && n >= 1 && n <= HSMA_TINY_MAX; }
+
+size_t tiny_item_bytes() { return sizeof(TinyItem); }
+
+// One problem with m, n <= 16 (a single call).
+hsma_status launch_tiny_one(bool cx, bool unit, int m, int n, cplx alpha, const double *A,
+                            int64_t lda, double *B, int64_t ldb, hipStream_t s) {
+    if (!tiny_fits(m, n)) return HSMA_INVALID_SIZE;
+    TinyItem one{A, B, lda, ldb, m, n, alpha.re, cx ? alpha.im : 0.0};
+    return cx ? tiny_t<true>(unit, one, nullptr, 1, s) : tiny_t<false>(unit, one, nullptr, 1, s);
+}
+
+// `count` items (device table, the batched item layout), four per workgroup.
+hsma_status launch_tiny_group(bool cx, bool unit, const void *items, int count, hipStream_t s) {
+    if (count <= 0) return HSMA_SUCCESS;
+    TinyItem none{};
+    const TinyItem *t = static_cast<const TinyItem *>(items);
+    return cx ? tiny_t<true>(unit, none, t, count, s) : tiny_t<false>(unit, none, t, count, s);
+}
+
+}  // namespace hsma

@@ -176,3 +176,30 @@ def test_more_items_than_one_grid_row():
     x1 = (b1 - l10 * x0) * (1.0 / l11)
     assert np.array_equal(X[:, 0], x0)
     assert np.array_equal(X[:, 1], x1)
+
+
+def test_fused_very_small_batch():
+    """Problems with m, n <= 16 run four per wavefront (the fused kernel),
+    alone and in batches: every one matches the oracle and its own single
+    call bit for bit, in a batch that also holds larger small problems and a
+    blocked one, with problems of both data types and diagonal kinds."""
+    rng = np.random.default_rng(77)
+    probs = []
+    for i in range(3001):
+        m, n = int(rng.integers(1, 17)), int(rng.integers(1, 17))
+        cx, unit = bool(i % 2), bool(i % 5 == 0)
+        L, B = W.problem(50000 + i, m, n, cx)
+        alpha = complex(rng.uniform(-2, 2), rng.uniform(-1, 1)) if cx else float(rng.uniform(-2, 2))
+        probs.append((L, B, alpha, unit))
+    probs += mixed_problems(9, 40, big=[(90, 20, True)])
+    dev = to_dev(probs)
+    hs.trsm_batched(dev)
+    torch.cuda.synchronize()
+    dev1 = to_dev(probs)
+    for L, B, a, u in dev1:
+        hs.trsm(L, B, a, unit=u)
+    torch.cuda.synchronize()
+    for k, ((L, B, a, u), (_, Bd, _, _), (_, Bs, _, _)) in enumerate(zip(probs, dev, dev1)):
+        X = hs.from_colmajor(Bd)
+        assert X.tobytes() == hs.from_colmajor(Bs).tobytes(), ("batched differs from single", k)
+        assert_parity(L, B, X, a, unit=u, tag=("fused", k, B.shape))
