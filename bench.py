@@ -70,7 +70,7 @@ def parse():
     ap.add_argument("--workload", default="default",
                     choices=["default", "large_real", "large_complex", "large_real_fp32",
                              "large_complex_fp32", "batched", "single", "mixed", "serving", "variants",
-                             "cholesky"])
+                             "cholesky", "tiny"])
     ap.add_argument("--ib", type=int, default=0, help="force I_B (0 = tuning table)")
     ap.add_argument("--m", type=int, default=0, help="override m (and n) for sweeps")
     ap.add_argument("--n", type=int, default=0)
@@ -613,6 +613,34 @@ def run_cholesky(args, torch, hs, sizes=((16384, False), (8192, True)), reps=3):
     return {"rows": rows, "flop_convention": "n^3/3 (complex 4 n^3/3)"}
 
 
+def run_tiny(args, torch, hs, count=100000, reps=10):
+    """Very small solves, fused four per wavefront: `count` complex problems
+    with m, n ~ U{1..16}, alpha = (1, 0.5), seed 6, as one resident plan;
+    solves/s and algorithmic HBM bytes/s; every 50th problem against the
+    oracle."""
+    import oracle
+    b = W.batched(seed=6, count=count, lo=1, hi=16, complex_=True, alpha=complex(1.0, 0.5))
+    pl, pb, vl, vb = hs.pack_batch(b.L, b.B)
+    pb0 = pb.clone()
+    plan = hs.BatchPlan([hs.problem_struct(L, B, b.alpha) for L, B in zip(vl, vb)])
+    plan.execute()
+    torch.cuda.synchronize()
+    worst = 0.0
+    for i in range(0, count, 50):
+        X = hs.from_colmajor(vb[i])
+        worst = max(worst, oracle.rel_err_fro(X, oracle.solve(b.L[i], b.B[i], b.alpha)))
+    pb.copy_(pb0)
+    ms = time_gpu(plan.execute, reps, 2, torch)
+    plan.close()
+    byts = b.total_bytes()
+    return {"workload": f"{count} complex solves, m, n ~ U{{1..16}}, alpha=(1,0.5), seed 6",
+            "ms_per_batch": round(ms, 4), "solves_per_s": round(count / (ms * 1e-3), 1),
+            "algorithmic_gbs": round(byts / (ms * 1e-3) / 1e9, 1),
+            "hbm_frac": round(byts / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "parity": {"sampled_problems": len(range(0, count, 50)), "worst_rel_err_fro": worst,
+                       "ok": bool(worst <= 1e-12)}}
+
+
 def run_graph(args, torch, hs, sizes=(256, 512, 1024), reps=30):
     """Blocked schedule replayed as a captured HIP graph vs launched eagerly,
     on mid-size DTRSMs where launch overhead matters (same inputs, results
@@ -908,6 +936,10 @@ def run_headline(args, torch, hs, names):
     torch.cuda.empty_cache()
     hs.workspace_release()
     try:
+        out["very_small_batched"] = run_tiny(sub, torch, hs)
+    except Exception as e:
+        out["very_small_batched"] = {"error": repr(e)}
+    try:
         out["cholesky"] = run_cholesky(sub, torch, hs)
     except Exception as e:
         out["cholesky"] = {"error": repr(e)}
@@ -978,6 +1010,11 @@ def main():
         res = run_serving(args, torch, hs)
         workload = (f"TRSM serving: Poisson {args.rate:.0f} req/s for {args.duration:.0f} s, m log-U[8,4096], "
                     f"n log-U[1,512], 70% real / 30% complex, seed 4")
+    elif args.workload == "tiny":
+        r = run_tiny(args, torch, hs, count=args.count or 100000)
+        res = {"value": r["solves_per_s"], "unit": "solves/s", "ms_per_step": r["ms_per_batch"],
+               "dtype": "c128", "pct_fp64_peak": None, "extra_config": {}, "very_small_batched": r}
+        workload = r["workload"]
     elif args.workload == "cholesky":
         r = run_cholesky(args, torch, hs)
         first = r["rows"][0]
@@ -1016,7 +1053,7 @@ def main():
                         "flop_convention": "real m^2 n; complex 4 m^2 n + 2 m n"}, **res["extra_config"]),
     }
     for k in ("solves_per_s", "gflops", "phases", "parity", "roofline", "rocblas", "cpu_baseline",
-              "mixed", "serving", "variants", "cholesky"):
+              "mixed", "serving", "variants", "cholesky", "very_small_batched"):
         if k in res:
             out[k] = res[k]
     if headline is not None:
