@@ -230,12 +230,16 @@ typedef struct {
                              the returned X from an FP64 residual on the GPU,
                              formed by one triangular product whose order of
                              summation is independent of the solve's */
-    int32_t use_graph;    /* 1: run the blocked schedule as a HIP graph captured
-                             on first use and replayed while (dtype, diag, m, n,
-                             A, lda, B, ldb, alpha, I_B, precision) repeat; the
-                             graph owns its workspace (hsma_graph_cache_clear
-                             frees it).  Ignored with refinement or the small
-                             path. */
+    int32_t use_graph;    /* 1: run the blocked schedule as a HIP graph, one
+                             per shape (dtype, diag, m, n, lda, ldb, I_B,
+                             precision): captured and instantiated on the
+                             shape's first call, replayed with one
+                             hipGraphLaunch after that, new A, B and alpha
+                             moved into it with hipGraphExecUpdate.  Replays
+                             of one shape run one after another on the device
+                             (they share the graph-owned workspace that
+                             hsma_graph_cache_clear frees).  Ignored with
+                             refinement or the small path. */
     int32_t reserved[2];  /* must be zero */
     double refine_tol;    /* target for refine_steps = -1 (0 means 1e-13) */
 } hsma_trsm_options;
@@ -272,6 +276,10 @@ hsma_status hsma_trsm_ex(hsma_diag diag, int64_t m, int64_t n, const void *alpha
 
 /* Destroy every cached graph and its workspace (waits for their work). */
 hsma_status hsma_graph_cache_clear(void);
+
+/* Graph-cache counters since the library was loaded: graphs instantiated,
+ * in-place argument updates, and replays.  Any pointer may be NULL. */
+hsma_status hsma_graph_stats(int64_t *captures, int64_t *updates, int64_t *replays);
 
 /*
  * Workspace cache.  The library keeps freed workspace blocks of the current

@@ -166,6 +166,8 @@ def lib():
         L.hsma_workspace_release.restype = i32
         L.hsma_graph_cache_clear.argtypes = []
         L.hsma_graph_cache_clear.restype = i32
+        L.hsma_graph_stats.argtypes = [ctypes.POINTER(i64)] * 3
+        L.hsma_graph_stats.restype = i32
         L.hsma_profile_begin.argtypes = []
         L.hsma_profile_begin.restype = i32
         L.hsma_profile_end.argtypes = [ctypes.POINTER(PhaseStat), ctypes.c_int]
@@ -487,6 +489,13 @@ def profile_end() -> dict:
 
 def graph_cache_clear() -> None:
     _check(lib().hsma_graph_cache_clear(), "hsma_graph_cache_clear")
+
+
+def graph_stats() -> dict:
+    """Graph-cache counters: instantiations, in-place updates, replays."""
+    c, u, r = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+    _check(lib().hsma_graph_stats(ctypes.byref(c), ctypes.byref(u), ctypes.byref(r)), "hsma_graph_stats")
+    return {"captures": c.value, "updates": u.value, "replays": r.value}
 
 
 def workspace_release() -> None:

@@ -211,3 +211,39 @@ def test_graph_replay_matches_eager_every_time():
             torch.cuda.synchronize()
         check(L, B, hs.from_colmajor(Bg), -1.0, tag=("graph", cx))
     hs.graph_cache_clear()
+
+
+def test_graph_one_capture_per_shape_new_pointers_and_alpha():
+    """One graph per shape: calls with other A, B and alpha of the same shape
+    replay the instantiated graphs with their arguments updated in place (no
+    new instantiation after the two the shape keeps), and every replay equals
+    the eager solve of its own inputs bit for bit, with eager work and a
+    second shape interleaved."""
+    hs.graph_cache_clear()
+    for cx, m, n, ib in ((False, 500, 70, 64), (True, 260, 33, 32)):
+        probs = [W.problem(70 + k, m, n, cx) for k in range(5)]
+        alphas = [(-1.0, 0.5, 2.0, -0.75, 1.0)[k] if not cx else complex(-1.0 + 0.25 * k, 0.5 - k)
+                  for k in range(5)]
+        dev = [(hs.to_colmajor(L), hs.to_colmajor(B)) for L, B in probs]
+        refs = []
+        for (L, B), a in zip(probs, alphas):
+            Le, Be = hs.to_colmajor(L), hs.to_colmajor(B)
+            hs.trsm(Le, Be, a, block_size=ib)
+            refs.append(Be)
+        torch.cuda.synchronize()
+        before = hs.graph_stats()
+        for rnd in range(3):
+            for k, ((Ld, Bd), a) in enumerate(zip(dev, alphas)):
+                Bd.copy_(hs.to_colmajor(probs[k][1]))
+                hs.trsm(Ld, Bd, a, block_size=ib, graph=True)
+                # another shape in between
+                L2, B2 = W.problem(99, 130, 7, cx)
+                hs.trsm(hs.to_colmajor(L2), hs.to_colmajor(B2), 1.0, block_size=32, graph=True)
+                torch.cuda.synchronize()
+                assert hs.from_colmajor(Bd).tobytes() == hs.from_colmajor(refs[k]).tobytes(), (cx, rnd, k)
+        after = hs.graph_stats()
+        # two graphs for this shape and two for the interleaved one, at most
+        assert after["captures"] - before["captures"] <= 4, (before, after)
+        assert after["updates"] - before["updates"] >= 10, (before, after)
+        assert after["replays"] - before["replays"] == 30
+    hs.graph_cache_clear()
