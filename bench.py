@@ -50,9 +50,10 @@ sys.path.insert(0, ROOT)
 # eight blocked-class streams; with HIP's default of 4 queues these share
 # in-order hardware queues, so a round's small solves wait behind other
 # streams' blocked chains (20 s runs at 20 000 requests/s: p50 22.1 ms, small
-# requests 17.0 ms with 4 queues; 16.3 ms and 10.3 ms with 12).  An existing
-# setting is kept.
-HW_QUEUES = int(os.environ.setdefault("GPU_MAX_HW_QUEUES", "12"))
+# requests 17.0 ms with 4 queues; 16.3 ms and 10.3 ms with 12).  The
+# benchmark process runs with 12 (HSMA_BENCH_HW_QUEUES overrides).
+os.environ["GPU_MAX_HW_QUEUES"] = os.environ.get("HSMA_BENCH_HW_QUEUES", "12")
+HW_QUEUES = int(os.environ["GPU_MAX_HW_QUEUES"])
 
 import workloads as W  # noqa: E402
 
@@ -112,6 +113,19 @@ class RocBlas:
                   self.lib.rocblas_ctrsm):
             f.argtypes = [vp, i32, i32, i32, i32, i32, i32, vp, vp, i32, vp, i32]
             f.restype = i32
+
+    def ztrsm_batched(self, m, n, alpha, A_ptrs, lda, B_ptrs, ldb, count):
+        """rocblas_ztrsm_batched (left, lower, no transpose, non-unit) on
+        device arrays of device pointers."""
+        f = self.lib.rocblas_ztrsm_batched
+        vp, i32 = ctypes.c_void_p, ctypes.c_int32
+        f.argtypes = [vp, i32, i32, i32, i32, i32, i32, vp, vp, i32, vp, i32, i32]
+        f.restype = i32
+        a = (ctypes.c_double * 2)(complex(alpha).real, complex(alpha).imag)
+        st = f(self.h, self.SIDE_LEFT, self.FILL_LOWER, self.OP_NONE, self.DIAG_NON_UNIT, m, n, a,
+               ctypes.c_void_p(A_ptrs), lda, ctypes.c_void_p(B_ptrs), ldb, count)
+        if st != 0:
+            raise RuntimeError(f"rocblas_ztrsm_batched: {st}")
 
     SIDE = {"L": 141, "R": 142}
     UPLO = {"U": 121, "L": 122}
@@ -388,10 +402,14 @@ def run_batched(args, torch, hs, cfg):
     ev_ms = ev0.elapsed_time(ev1) / args.steps
     fl = b.total_flops()
     byts = b.total_bytes()
+    # The dominant kernel is the small-solve kernel; problems with m, n <= 16
+    # run in the fused kernel's own (short) launch and are left out of its bytes.
+    tiny = [(m_, n_) for m_, n_ in b.shapes if m_ <= 16 and n_ <= 16]
+    byts_small = byts - sum(W.algorithmic_bytes(m_, n_, True) for m_, n_ in tiny)
     sm = prof["small"]
     launches = max(1, sm["launches"] // args.steps)
     avg_launch_ms = sm["ms"] / max(1, sm["launches"])
-    bytes_per_launch = byts / launches
+    bytes_per_launch = byts_small / launches
     ach = bytes_per_launch / (avg_launch_ms * 1e-3) / 1e9
     traffic = measured_traffic("small_solve_batched10000_traffic", SMALL_SOURCES, count == cfg["count"])
     roof = {"bound": "hbm", "kernel": "hsma_small_solve (grouped, one workgroup per item)",
@@ -399,12 +417,15 @@ def run_batched(args, torch, hs, cfg):
             "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic,
             "avg_launch_ms": avg_launch_ms, "launches_per_step": launches,
             "bytes_per_launch": bytes_per_launch, "bytes_per_step": byts,
+            "fused_very_small_problems": len(tiny),
+            "fused_launch_ms_per_step": prof["tiny"]["ms"] / args.steps,
             "step_ms_events": ev_ms,
             "step_rate_gbs": round(byts / (ev_ms * 1e-3) / 1e9, 2),
             "per_unit": "per problem: 16 (m(m+1)/2 + 2mn) bytes (lower triangle of L once, B read and "
                         "written once); a launch serves one (dtype, diag) group, so bytes per "
-                        "launch = bytes per step / group launches per step (one here: every problem is "
-                        "complex with a non-unit diagonal)"}
+                        "launch = bytes of the group's problems (one group here: every problem is "
+                        "complex with a non-unit diagonal; the problems with m, n <= 16 run in the "
+                        "fused kernel's launch and are not counted)"}
 
     # One-shot API (host descriptors uploaded each call) for reference.
     oneshot_ms = time_gpu(lambda: hs.trsm_batched(probs), max(2, args.steps), 1, torch)
@@ -421,6 +442,26 @@ def run_batched(args, torch, hs, cfg):
             rms = time_gpu(rb_loop, 2, 1, torch)
             rocblas = {"kind": "rocblas_ztrsm called once per problem", "ms_per_step": round(rms, 3),
                        "solves_per_s": round(count / (rms * 1e-3), 1), "speedup_ours": round(rms / ms, 2)}
+            # rocBLAS's batched call on each uniform (m, n) group of the batch
+            groups = {}
+            for i, (m_, n_) in enumerate(b.shapes):
+                groups.setdefault((m_, n_), []).append(i)
+            ptrs = []
+            for (m_, n_), idx in groups.items():
+                pa = torch.tensor([vl[i].data_ptr() for i in idx], dtype=torch.int64, device="cuda")
+                pbp = torch.tensor([vb[i].data_ptr() for i in idx], dtype=torch.int64, device="cuda")
+                ptrs.append((m_, n_, pa, pbp, len(idx)))
+            pb.copy_(pb0)
+
+            def rb_groups():
+                for m_, n_, pa, pbp, cnt in ptrs:
+                    rb.ztrsm_batched(m_, n_, b.alpha, pa.data_ptr(), m_, pbp.data_ptr(), m_, cnt)
+            gms = time_gpu(rb_groups, 3, 1, torch)
+            rocblas_batched = {"kind": "rocblas_ztrsm_batched once per uniform (m, n) group",
+                               "groups": len(ptrs), "ms_per_step": round(gms, 3),
+                               "solves_per_s": round(count / (gms * 1e-3), 1),
+                               "speedup_ours": round(gms / ms, 2)}
+            rocblas = {"per_problem_loop": rocblas, "batched_per_shape": rocblas_batched}
         except Exception as e:
             rocblas = {"error": str(e)}
 
@@ -908,6 +949,57 @@ def run_serving(args, torch, hs):
     }
 
 
+def run_baselines(args, torch, hs):
+    """Reference rates next to the results: the matrix-core peaks this GPU
+    sustains (beside the datasheet's), a plain device copy's bandwidth, and
+    the oracle on the host for the single, large and mixed workloads, on all
+    threads and on one (bounded samples of the same work)."""
+    import oracle
+    p64, g64 = hs.mfma_peak(False)
+    p32, g32 = hs.mfma_peak(True)
+    out = {"fp64_mfma_tflops_measured": round(p64, 2), "fp64_probe_shader_ghz": round(g64, 3),
+           "fp64_datasheet_tflops": FP64_PEAK_TFLOPS,
+           "fp32_mfma_tflops_measured": round(p32, 2), "fp32_probe_shader_ghz": round(g32, 3),
+           "fp32_datasheet_tflops": FP32_PEAK_TFLOPS}
+    src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    cms = time_gpu(lambda: dst.copy_(src), 10, 2, torch)
+    out["device_copy_gbs"] = round(2 * src.numel() * 8 / (cms * 1e-3) / 1e9, 1)
+    out["hbm_datasheet_gbs"] = HBM_PEAK_GBS
+    del src, dst
+    torch.cuda.empty_cache()
+    threads = oracle.num_threads()
+    cpu = {}
+    try:
+        # single small solve: 10 calls, mean of the last 9 (the paper's method) and median
+        L, B = W.problem(0, 32, 32, False)
+        for t in (threads, 1):
+            oracle.set_num_threads(t)
+            ts = []
+            for _ in range(10):
+                t0 = time.perf_counter()
+                oracle.solve(L, B, 1.0)
+                ts.append((time.perf_counter() - t0) * 1e6)
+            cpu[f"single_32_threads{t}"] = {"us_mean_last9": round(float(np.mean(ts[1:])), 2),
+                                            "us_median": round(float(np.median(ts)), 2)}
+        for key, cfg in (("large_real_16384", W.LARGE_REAL), ("large_complex_8192", W.LARGE_COMPLEX)):
+            L, B = W.problem(cfg["seed"], cfg["m"], cfg["n"], cfg["complex_"])
+            for t in (threads, 1):
+                oracle.set_num_threads(t)
+                cpu[f"{key}_threads{t}"] = cpu_oracle_columns(L, B, cfg["alpha"], 4.0, cfg["complex_"])
+            del L, B
+        L, B = W.mixed_problem(W.MIXED["m"], W.MIXED["n"], 1e3, seed=W.MIXED["seed"])
+        for t in (threads, 1):
+            oracle.set_num_threads(t)
+            cpu[f"mixed_8192x4096_threads{t}"] = cpu_oracle_columns(L, B, 1.0, 4.0, False)
+        del L, B
+    finally:
+        oracle.set_num_threads(threads)
+    out["oracle_cpu"] = cpu
+    out["host_threads"] = threads
+    return out
+
+
 def run_headline(args, torch, hs, names):
     """The rest of the headline metric in the same run: the large DTRSM and
     ZTRSM solves, a lone small solve, graph replay, mixed precision and the
@@ -917,6 +1009,10 @@ def run_headline(args, torch, hs, names):
     sub = copy.copy(args)
     sub.no_cpu_baseline = True
     sub.steps, sub.warmup = 3, 1
+    try:
+        out["baselines"] = run_baselines(sub, torch, hs)
+    except Exception as e:  # reported, not fatal
+        out["baselines"] = {"error": repr(e)}
     for key in ("large_real", "large_complex", "large_real_fp32", "large_complex_fp32"):
         cfg = dict({"large_real": W.LARGE_REAL, "large_complex": W.LARGE_COMPLEX,
                     "large_real_fp32": dict(W.LARGE_REAL, fp32=True),

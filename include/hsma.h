@@ -274,6 +274,20 @@ hsma_status hsma_trsm_ex(hsma_diag diag, int64_t m, int64_t n, const void *alpha
                          hsma_dtype dtype, const hsma_trsm_options *opts,
                          hsma_trsm_report *report, hsma_stream_t stream);
 
+/*
+ * hsma_mfma_peak -- measure the matrix-core rate of the current device: FP64
+ * (fp32 == 0, v_mfma_f64_16x16x4_f64) or FP32 (fp32 == 1,
+ * v_mfma_f32_16x16x4_f32) instructions on register operands, 16 independent
+ * accumulator chains per wavefront, `iters` iterations, 32 wavefronts per CU;
+ * *tflops receives the sustained TFLOP/s (2048 flops per instruction per
+ * wavefront).  *shader_ghz (may be NULL) receives the clock the CUs ran at
+ * during the loop (shader-clock cycles over constant-rate wall-clock time).
+ * A measurement aid for the roofline fractions (datasheet peaks: 78.6 FP64,
+ * 157.3 FP32 TFLOP/s); synchronises the null stream.  Errors: tflops NULL ->
+ * HSMA_INVALID_POINTER; iters outside 1..2^24 -> HSMA_INVALID_SIZE.
+ */
+hsma_status hsma_mfma_peak(int32_t fp32, int64_t iters, double *tflops, double *shader_ghz);
+
 /* Destroy every cached graph and its workspace (waits for their work). */
 hsma_status hsma_graph_cache_clear(void);
 
@@ -365,7 +379,8 @@ typedef enum {
     HSMA_PHASE_OTHER = 4,     /* zero fills, conversions, residuals, norms */
     HSMA_PHASE_FACTOR = 5,    /* Cholesky diagonal blocks and trailing
                                  Hermitian updates (hsma_potrf) */
-    HSMA_PHASE_COUNT = 6
+    HSMA_PHASE_TINY = 6,      /* fused very small solves (m, n <= 16) */
+    HSMA_PHASE_COUNT = 7
 } hsma_phase;
 
 typedef struct {

@@ -115,9 +115,9 @@ BACKEND_HIP, BACKEND_SIMULATED = 0, 1
 INPUT_DEVICE, INPUT_SYNTHETIC = 0, 1
 
 
-PHASE_DIAG_INV, PHASE_UPDATE, PHASE_LEAF, PHASE_SMALL, PHASE_OTHER, PHASE_FACTOR = range(6)
-PHASE_COUNT = 6
-PHASE_NAMES = ["diag_inv", "update", "leaf_solve", "small", "other", "factor"]
+PHASE_DIAG_INV, PHASE_UPDATE, PHASE_LEAF, PHASE_SMALL, PHASE_OTHER, PHASE_FACTOR, PHASE_TINY = range(7)
+PHASE_COUNT = 7
+PHASE_NAMES = ["diag_inv", "update", "leaf_solve", "small", "other", "factor", "tiny"]
 
 _lib = None
 
@@ -166,6 +166,9 @@ def lib():
         L.hsma_workspace_release.restype = i32
         L.hsma_graph_cache_clear.argtypes = []
         L.hsma_graph_cache_clear.restype = i32
+        L.hsma_mfma_peak.argtypes = [i32, i64, ctypes.POINTER(ctypes.c_double),
+                                     ctypes.POINTER(ctypes.c_double)]
+        L.hsma_mfma_peak.restype = i32
         L.hsma_graph_stats.argtypes = [ctypes.POINTER(i64)] * 3
         L.hsma_graph_stats.restype = i32
         L.hsma_profile_begin.argtypes = []
@@ -489,6 +492,15 @@ def profile_end() -> dict:
 
 def graph_cache_clear() -> None:
     _check(lib().hsma_graph_cache_clear(), "hsma_graph_cache_clear")
+
+
+def mfma_peak(fp32: bool = False, iters: int = 10000):
+    """(sustained matrix-core TFLOP/s, shader clock GHz during the run) of
+    this GPU for FP64 or FP32 MFMA."""
+    t, g = ctypes.c_double(), ctypes.c_double()
+    _check(lib().hsma_mfma_peak(1 if fp32 else 0, iters, ctypes.byref(t), ctypes.byref(g)),
+           "hsma_mfma_peak")
+    return t.value, g.value
 
 
 def graph_stats() -> dict:

@@ -188,8 +188,18 @@ static hsma_status run_large(const std::vector<hsma_problem> &large, hipStream_t
 static hsma_status run_table(const BatchTable &t, hipStream_t s, bool fork = true) {
     DevicePool *pool;
     HSMA_TRY(pool_for(&pool));
+    // Fused very small groups run on s itself, first: they are short, and a
+    // fork and join would cost more than they take.  The other groups fork
+    // when there are several.
+    for (int g = 0; g < kGroups; ++g) {
+        if (t.count[g] == 0 || !group_is_tiny(g)) continue;
+        const bool cx = g >= 16, unit = (g / 8) % 2;
+        const void *items = static_cast<const unsigned char *>(t.dev) + (size_t)t.start[g] * sizeof(Item);
+        ProfScope prof(HSMA_PHASE_TINY, 0.0, s);
+        HSMA_TRY(launch_tiny_group(cx, unit, items, t.count[g], s));
+    }
     int ngroups = 0;
-    for (int g = 0; g < kGroups; ++g) ngroups += t.count[g] > 0;
+    for (int g = 0; g < kGroups; ++g) ngroups += t.count[g] > 0 && !group_is_tiny(g);
     if (!t.large.empty()) ngroups += 1;
     if (ngroups > 0) {
         // One launch (or no fork) stays on s: no events.
@@ -204,7 +214,7 @@ static hsma_status run_table(const BatchTable &t, hipStream_t s, bool fork = tru
         hsma_status st = HSMA_SUCCESS;
         // Largest-row groups first: they hold the longest items.
         for (int g = kGroups - 1; g >= 0 && st == HSMA_SUCCESS; --g) {
-            if (t.count[g] == 0) continue;
+            if (t.count[g] == 0 || group_is_tiny(g)) continue;
             hipStream_t fs = forking ? pool->fork[k++ % kForkStreams] : s;
             if (fs != s) HSMA_HIP(hipStreamWaitEvent(fs, fork_ev, 0));
             const bool cx = g >= 16, unit = (g / 8) % 2;
@@ -213,11 +223,8 @@ static hsma_status run_table(const BatchTable &t, hipStream_t s, bool fork = tru
             const void *items = base + (size_t)t.start[g] * sizeof(Item);
             {
                 ProfScope prof(HSMA_PHASE_SMALL, 0.0, fs);
-                if (group_is_tiny(g))
-                    st = launch_tiny_group(cx, unit, items, t.count[g], fs);
-                else
-                    st = cx ? launch_small_group_z(unit, nch, items, t.count[g], fs)
-                            : launch_small_group_d(unit, nch, items, t.count[g], fs);
+                st = cx ? launch_small_group_z(unit, nch, items, t.count[g], fs)
+                        : launch_small_group_d(unit, nch, items, t.count[g], fs);
             }
             if (fs != s) {
                 hipEvent_t j;

@@ -8,7 +8,8 @@
 //     L21 = A21 inv(L11)^H            the right-side, conjugate-transpose TRSM
 //     A22 <- A22 - L21 L21^H          lower triangle only, FP64 matrix cores
 //     L22 = chol(A22)
-// with diagonal blocks of at most 64 rows factored in LDS by one wavefront.
+// with diagonal blocks of at most 64 rows factored by one wavefront, a row
+// per lane in registers.
 // The split point is a multiple of 64, so every base block is whole except
 // the last.  The solve L L^H X = B is two TRSMs: L Y = B, then L^H X = Y.
 //
@@ -62,38 +63,49 @@ struct Z<true> {
     static __device__ __forceinline__ V real(double d) { return V{d, 0.0}; }
 };
 
-// One n x n diagonal block (n <= 64) factored in LDS, right-looking:
-// column j is scaled by 1/sqrt(pivot), then lane c updates column c of the
-// trailing lower triangle.  LDS is row-major (a[i][c]) so the lanes of an
-// update touch consecutive words.
+// One n x n diagonal block (n <= 64), right-looking, in registers: lane i
+// holds row i of the lower triangle (a_ic, c <= i).  At step j lane j
+// publishes sqrt(a_jj); every lane below scales its a_ij by the reciprocal
+// and publishes it, then updates its own row, a_ic -= l_ij conj(l_cj) for
+// j < c <= i, reading column j from LDS (a broadcast: all lanes read the same
+// l_cj).  Rows are loaded and stored column by column, consecutive lanes on
+// consecutive rows.
 template <bool CX>
 __global__ __launch_bounds__(64) void hsma_potrf_base(double *__restrict__ A, int64_t lda, int n) {
     typedef Z<CX> O;
     typedef typename O::V V;
-    __shared__ V a[kBase][kBase + 1];
-    const int t = threadIdx.x;
-    for (int e = t; e < n * n; e += 64) {
-        const int i = e % n, j = e / n;
-        if (i >= j) a[i][j] = O::ld(A, i + (int64_t)j * lda);
-    }
-    __syncthreads();
-    for (int j = 0; j < n; ++j) {
-        const double d = sqrt(O::re(a[j][j]));
-        const double r = 1.0 / d;
-        __syncthreads();
-        if (t > j && t < n) a[t][j] = O::scale(a[t][j], r);
-        if (t == j) a[j][j] = O::real(d);
-        __syncthreads();
-        if (t > j && t < n) {
-            const V lc = a[t][j];
-            for (int i = t; i < n; ++i) a[i][t] = O::fnms_conj(a[i][t], a[i][j], lc);
+    __shared__ V colj[kBase];
+    __shared__ double piv;
+    const int i = threadIdx.x;
+    const bool row_ok = i < n;
+    V r[kBase];
+#pragma unroll
+    for (int c = 0; c < kBase; ++c)
+        r[c] = (row_ok && c <= i && c < n) ? O::ld(A, i + (int64_t)c * lda) : O::real(0.0);
+#pragma unroll
+    for (int j = 0; j < kBase; ++j) {
+        if (j < n) {
+            if (i == j) piv = sqrt(O::re(r[j]));
+            __syncthreads();
+            const double d = piv;
+            if (i == j) r[j] = O::real(d);
+            if (i > j && row_ok) {
+                r[j] = O::scale(r[j], 1.0 / d);
+                colj[i] = r[j];
+            }
+            __syncthreads();
+            if (i > j && row_ok) {
+                const V lij = r[j];
+#pragma unroll
+                for (int c = j + 1; c < kBase; ++c)
+                    if (c <= i) r[c] = O::fnms_conj(r[c], lij, colj[c]);
+            }
+            __syncthreads();  // column j read before the next step writes
         }
-        __syncthreads();
     }
-    for (int e = t; e < n * n; e += 64) {
-        const int i = e % n, j = e / n;
-        if (i >= j) O::st(A, i + (int64_t)j * lda, a[i][j]);
-    }
+#pragma unroll
+    for (int c = 0; c < kBase; ++c)
+        if (row_ok && c <= i && c < n) O::st(A, i + (int64_t)c * lda, r[c]);
 }
 
 hsma_status potrf_base(bool cx, int n, double *A, int64_t lda, hipStream_t s) {

@@ -35,8 +35,12 @@ hsma_status launch_small_solve(bool cplx_, bool unit, int m, int64_t n, cplx alp
                                const double *A, int64_t lda, double *B, int64_t ldb,
                                hipStream_t s) {
     if (m < 1 || m > 64) return HSMA_INVALID_SIZE;
-    ProfScope prof(HSMA_PHASE_SMALL, (cplx_ ? 8.0 : 2.0) * 0.5 * m * (m + 1.0) * (double)n, s);
-    if (tiny_fits(m, n)) return launch_tiny_one(cplx_, unit, m, (int)n, alpha, A, lda, B, ldb, s);
+    const double flops = (cplx_ ? 8.0 : 2.0) * 0.5 * m * (m + 1.0) * (double)n;
+    if (tiny_fits(m, n)) {
+        ProfScope prof(HSMA_PHASE_TINY, flops, s);
+        return launch_tiny_one(cplx_, unit, m, (int)n, alpha, A, lda, B, ldb, s);
+    }
+    ProfScope prof(HSMA_PHASE_SMALL, flops, s);
     return cplx_ ? launch_small_z(unit, m, n, alpha, A, lda, B, ldb, s)
                  : launch_small_d(unit, m, n, alpha, A, lda, B, ldb, s);
 }
