@@ -18,7 +18,8 @@ namespace {
 typedef double dbl4 __attribute__((ext_vector_type(4)));
 typedef float flt4 __attribute__((ext_vector_type(4)));
 
-constexpr int kChains = 8;
+constexpr int kChains64 = 8;   // FP64 chains: enough to cover that instruction's latency
+constexpr int kChains32 = 16;  // FP32 issues twice as fast, so twice the chains in flight
 constexpr int kUnroll = 32;  // iterations per loop trip (iters is rounded down to a multiple); the
                              // compiler copies FP64 accumulators across the loop back-edge, so
                              // long trips keep those copies a few percent of the issue slots
@@ -27,21 +28,21 @@ constexpr int kUnroll = 32;  // iterations per loop trip (iters is rounded down 
 // loop; every thread then writes its reduction at 2 + its index.
 __global__ __launch_bounds__(256) void hsma_peak_f64(int64_t iters, double *__restrict__ sink) {
     const double a = 1.0 + 1e-9 * threadIdx.x, b = 1.0 - 1e-9 * blockIdx.x;
-    dbl4 acc[kChains];
+    dbl4 acc[kChains64];
 #pragma unroll
-    for (int c = 0; c < kChains; ++c) acc[c] = dbl4{0.0, 0.0, 0.0, 0.0};
+    for (int c = 0; c < kChains64; ++c) acc[c] = dbl4{0.0, 0.0, 0.0, 0.0};
     const uint64_t c0 = clock64(), w0 = wall_clock64();
     const int outer = (int)(iters / kUnroll);
     for (int it = 0; it < outer; ++it) {
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u)
 #pragma unroll
-            for (int c = 0; c < kChains; ++c) acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[c], 0, 0, 0);
+            for (int c = 0; c < kChains64; ++c) acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[c], 0, 0, 0);
     }
     const uint64_t c1 = clock64(), w1 = wall_clock64();
     double s = 0.0;
 #pragma unroll
-    for (int c = 0; c < kChains; ++c) s += acc[c][0] + acc[c][1] + acc[c][2] + acc[c][3];
+    for (int c = 0; c < kChains64; ++c) s += acc[c][0] + acc[c][1] + acc[c][2] + acc[c][3];
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         sink[0] = (double)(c1 - c0);
         sink[1] = (double)(w1 - w0);
@@ -51,21 +52,21 @@ __global__ __launch_bounds__(256) void hsma_peak_f64(int64_t iters, double *__re
 
 __global__ __launch_bounds__(256) void hsma_peak_f32(int64_t iters, double *__restrict__ sink) {
     const float a = 1.0f + 1e-6f * threadIdx.x, b = 1.0f - 1e-6f * blockIdx.x;
-    flt4 acc[kChains];
+    flt4 acc[kChains32];
 #pragma unroll
-    for (int c = 0; c < kChains; ++c) acc[c] = flt4{0.f, 0.f, 0.f, 0.f};
+    for (int c = 0; c < kChains32; ++c) acc[c] = flt4{0.f, 0.f, 0.f, 0.f};
     const uint64_t c0 = clock64(), w0 = wall_clock64();
     const int outer = (int)(iters / kUnroll);
     for (int it = 0; it < outer; ++it) {
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u)
 #pragma unroll
-            for (int c = 0; c < kChains; ++c) acc[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[c], 0, 0, 0);
+            for (int c = 0; c < kChains32; ++c) acc[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[c], 0, 0, 0);
     }
     const uint64_t c1 = clock64(), w1 = wall_clock64();
     float s = 0.f;
 #pragma unroll
-    for (int c = 0; c < kChains; ++c) s += acc[c][0] + acc[c][1] + acc[c][2] + acc[c][3];
+    for (int c = 0; c < kChains32; ++c) s += acc[c][0] + acc[c][1] + acc[c][2] + acc[c][3];
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         sink[0] = (double)(c1 - c0);
         sink[1] = (double)(w1 - w0);
@@ -111,7 +112,7 @@ extern "C" hsma_status hsma_mfma_peak(int32_t fp32, int64_t iters, double *tflop
         if (he == hipSuccess) he = hipMemcpy(clk, sink, sizeof(clk), hipMemcpyDeviceToHost);
         if (he == hipSuccess) {
             // 16 x 16 x 4 multiply-adds = 2048 flops per instruction per wavefront
-            const double flops = 2048.0 * kChains * (double)(iters / kUnroll * kUnroll) * blocks * 4;
+            const double flops = 2048.0 * (fp32 ? kChains32 : kChains64) * (double)(iters / kUnroll * kUnroll) * blocks * 4;
             *tflops = flops / (ms * 1e-3) / 1e12;
             if (shader_ghz)
                 *shader_ghz = (clk[1] > 0 && wall_khz > 0) ? clk[0] / (clk[1] / (wall_khz * 1e3)) / 1e9 : 0.0;

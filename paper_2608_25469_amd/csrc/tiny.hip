@@ -41,8 +41,8 @@ struct D;
 template <>
 struct D<false> {
     typedef double V;
-    static __device__ __forceinline__ V ld(const double *p, int64_t i) { return p[i]; }
-    static __device__ __forceinline__ void st(double *p, int64_t i, V v) { p[i] = v; }
+    static __device__ __forceinline__ V ld(const HSMA_GLOBAL double *p, int64_t i) { return p[i]; }
+    static __device__ __forceinline__ void st(HSMA_GLOBAL double *p, int64_t i, V v) { p[i] = v; }
     static __device__ __forceinline__ V zero() { return 0.0; }
     static __device__ __forceinline__ V one() { return 1.0; }
     static __device__ __forceinline__ V mul(V a, V b) { return a * b; }
@@ -53,11 +53,11 @@ struct D<false> {
 template <>
 struct D<true> {
     typedef dbl2u V;
-    static __device__ __forceinline__ V ld(const double *p, int64_t i) {
-        return *reinterpret_cast<const dbl2u *>(p + 2 * i);
+    static __device__ __forceinline__ V ld(const HSMA_GLOBAL double *p, int64_t i) {
+        return *reinterpret_cast<const HSMA_GLOBAL dbl2u *>(p + 2 * i);
     }
-    static __device__ __forceinline__ void st(double *p, int64_t i, V v) {
-        *reinterpret_cast<dbl2u *>(p + 2 * i) = v;
+    static __device__ __forceinline__ void st(HSMA_GLOBAL double *p, int64_t i, V v) {
+        *reinterpret_cast<HSMA_GLOBAL dbl2u *>(p + 2 * i) = v;
     }
     static __device__ __forceinline__ V zero() { return V{0.0, 0.0}; }
     static __device__ __forceinline__ V one() { return V{1.0, 0.0}; }
@@ -92,42 +92,45 @@ __global__ __launch_bounds__(64) void hsma_tiny(TinyItem one, const TinyItem *__
     // alpha == 0: B <- 0, and neither A nor B is read (A may be null).
     const bool azero = it.ar == 0.0 && (!CX || it.ai == 0.0);
     const int m = (active && !azero) ? it.m : 0;
-    const double *A = (const double *)(const HSMA_GLOBAL double *)it.A;
-    // Stage the quarter's lower triangle (16 x 16, ld 17); zero elsewhere.
-    for (int e = lane; e < kMax * kMax; e += 16) {
-        const int i = e % kMax, k = e / kMax;
-        V v = O::zero();
-        if (i < m && k < m) {
-            if (k < i) v = O::ld(A, i + (int64_t)k * it.lda);
-            else if (k == i) v = UNIT ? O::one() : O::ld(A, i + (int64_t)k * it.lda);
-        } else if (i == k) {
-            v = O::one();
-        }
-        L[i + k * (kMax + 1)] = v;
+    const HSMA_GLOBAL double *A = (const HSMA_GLOBAL double *)it.A;
+    // Stage the quarter's lower triangle (16 x 16, ld 17; zero elsewhere):
+    // lane i of the quarter takes row i of every column, so each column is
+    // one contiguous read, and the unrolled loop issues all 16 loads before
+    // the first LDS store waits for one.
+    const int i = lane;
+    V lv[kMax];
+#pragma unroll
+    for (int k = 0; k < kMax; ++k) {
+        const bool rd = i < m && k < m && (UNIT ? k < i : k <= i);
+        lv[k] = rd ? O::ld(A, i + (int64_t)k * it.lda) : (i == k ? O::one() : O::zero());
     }
+#pragma unroll
+    for (int k = 0; k < kMax; ++k) L[i + k * (kMax + 1)] = lv[k];
     __syncthreads();
     if (!active || lane >= it.ncols) return;
-    double *col = (double *)(HSMA_GLOBAL double *)it.B + (CX ? 2 : 1) * (int64_t)lane * it.ldb;
+    HSMA_GLOBAL double *col = (HSMA_GLOBAL double *)it.B + (CX ? 2 : 1) * (int64_t)lane * it.ldb;
     if (azero) {
-        for (int i = 0; i < it.m; ++i) O::st(col, i, O::zero());
+        for (int r = 0; r < it.m; ++r) O::st(col, r, O::zero());
         return;
     }
     const V alpha = O::make(it.ar, it.ai);
     V x[kMax];
 #pragma unroll
-    for (int i = 0; i < kMax; ++i) x[i] = i < m ? O::mul(alpha, O::ld(col, i)) : O::zero();
+    for (int r = 0; r < kMax; ++r) x[r] = r < m ? O::ld(col, r) : O::zero();  // all loads in flight
+#pragma unroll
+    for (int r = 0; r < kMax; ++r) x[r] = O::mul(alpha, x[r]);
 #pragma unroll
     for (int k = 0; k < kMax; ++k) {
         if (k < m) {
             if (!UNIT) x[k] = O::div(x[k], L[k + k * (kMax + 1)]);
             const V xk = x[k];
 #pragma unroll
-            for (int i = k + 1; i < kMax; ++i) x[i] = O::fnms(x[i], L[i + k * (kMax + 1)], xk);
+            for (int r = k + 1; r < kMax; ++r) x[r] = O::fnms(x[r], L[r + k * (kMax + 1)], xk);
         }
     }
 #pragma unroll
-    for (int i = 0; i < kMax; ++i)
-        if (i < m) O::st(col, i, x[i]);
+    for (int r = 0; r < kMax; ++r)
+        if (r < m) O::st(col, r, x[r]);
 }
 
 template <bool CX>
