@@ -1,14 +1,18 @@
 // Many independent solves per call (the paper lists batched TRSM as future
 // work, Sec. 6).
 //
-// Problems with m <= 64 become work items -- one per 64-column panel -- of
-// the small-solve kernel, one workgroup per item.  Items are grouped by (data
-// type, diagonal kind); inside a group items are ordered by decreasing cost
-// (longest processing time first; the hardware starts workgroups in that
-// order).  The item table is uploaded in one copy; the group launches are
-// forked onto library-owned streams so they overlap on the device, and
-// joined back into the caller's stream.  Problems with m > 64
-// take the grouped blocked path (grouped.cpp) on one more forked stream.
+// Problems with m <= 64 are cut into strips of at most 16 columns for the
+// strip kernel (strip.hip), four strips per wavefront: the strips of a
+// wavefront share m (and whether alpha is zero) but may come from different
+// problems, so a problem occupies ceil(n / 16) quarter-wavefronts rather than
+// a whole wavefront.  Strips are grouped by (data type, diagonal kind); inside
+// a group the wavefronts are ordered by decreasing m (longest processing time
+// first: the hardware starts workgroups in that order).  Problems with m, n
+// <= 16 go to the fused very-small kernel instead.  The descriptor table is
+// uploaded in one copy; the group launches are forked onto library-owned
+// streams so they overlap on the device, and joined back into the caller's
+// stream.  Problems with m > 64 take the grouped blocked path (grouped.cpp)
+// on one more forked stream.
 
 #include <algorithm>
 #include <cstring>
@@ -28,10 +32,9 @@ hsma_status trsm_impl(hsma_diag diag, int64_t m, int64_t n, const void *alpha, c
 // From grouped.cpp
 hsma_status grouped_blocked(const hsma_problem *probs, int64_t count, hipStream_t s);
 
-// From small_d.hip / small_z.hip
-hsma_status launch_small_group_d(bool unit, int nch, const void *items, int count, hipStream_t s);
-hsma_status launch_small_group_z(bool unit, int nch, const void *items, int count, hipStream_t s);
-size_t small_item_bytes_d();
+// From strip.hip
+hsma_status launch_strip_group(bool cx, bool unit, const void *rows, int waves, hipStream_t s);
+size_t strip_item_bytes();
 
 namespace {
 
@@ -44,19 +47,19 @@ struct Item {
     double ar, ai;
 };
 
-constexpr int kGroups = 2 * 2 * 8;  // complex x unit x kernel instance (one used per pair)
+constexpr int kGroups = 2 * 2 * 2;  // complex x unit x (very small, strips)
 constexpr int kForkStreams = 8;
 
-// Every small item of a (data type, diagonal kind) runs in one launch of the
-// 64-row instance: its left-looking walk skips the 16-row blocks past each
-// item's m, so the work still follows m, and one launch keeps the whole GPU
-// on one longest-first queue instead of several launches competing for it.
 // Problems with m, n <= HSMA_TINY_MAX form their own group (slot 0 of the
-// pair), solved four per workgroup by the fused kernel.
+// pair), solved four per workgroup by the fused kernel; the others are cut
+// into strips (slot 1).
 int group_of(bool cx, bool unit, int m, int64_t n) {
-    return ((cx ? 1 : 0) * 2 + (unit ? 1 : 0)) * 8 + (tiny_fits(m, n) ? 0 : 7);
+    return ((cx ? 1 : 0) * 2 + (unit ? 1 : 0)) * 2 + (tiny_fits(m, n) ? 0 : 1);
 }
-bool group_is_tiny(int g) { return g % 8 == 0; }
+bool group_is_tiny(int g) { return g % 2 == 0; }
+bool group_cx(int g) { return g >= 4; }
+bool group_unit(int g) { return (g / 2) % 2 == 1; }
+constexpr int kStripCols = 16;
 
 struct DevicePool {
     bool init = false;
@@ -98,6 +101,8 @@ hsma_status pool_for(DevicePool **out) {
 struct BatchTable {
     void *dev = nullptr;  // items, grouped and sorted
     size_t bytes = 0;
+    // Per group: first item, and the launch size -- items of a very small
+    // group, wavefronts (four items each) of a strip group.
     int start[kGroups] = {}, count[kGroups] = {};
     std::vector<hsma_problem> large;
 };
@@ -123,8 +128,11 @@ static hsma_status check_all(const hsma_problem *probs, int64_t count, int64_t *
 // Host image of the table: items grouped and sorted.
 static void build_image(const hsma_problem *probs, int64_t count, BatchTable *t,
                         std::vector<unsigned char> *img) {
-    std::vector<Item> groups[kGroups];
-    std::vector<double> costs[kGroups];
+    // Very small problems: one item each, by decreasing cost.
+    std::vector<Item> tiny[kGroups];
+    std::vector<double> tiny_cost[kGroups];
+    // Strips, bucketed per group by (m, alpha == 0): bucket 2 m + azero.
+    std::vector<Item> strips[kGroups][2 * 65];
     for (int64_t i = 0; i < count; ++i) {
         const hsma_problem &p = probs[i];
         if (p.m == 0 || p.n == 0) continue;
@@ -135,36 +143,59 @@ static void build_image(const hsma_problem *probs, int64_t count, BatchTable *t,
         const bool cx = p.dtype == HSMA_C64F, unit = p.diag == HSMA_UNIT;
         const int g = group_of(cx, unit, (int)p.m, p.n);
         const int es = cx ? 2 : 1;
-        for (int64_t c0 = 0; c0 < p.n; c0 += 64) {
-            Item it;
-            it.A = static_cast<const double *>(p.A);
-            it.B = static_cast<double *>(p.B) + es * c0 * p.ldb;
-            it.lda = p.lda;
-            it.ldb = p.ldb;
-            it.m = (int32_t)p.m;
-            it.ncols = (int32_t)std::min<int64_t>(64, p.n - c0);
-            it.ar = p.alpha_re;
-            it.ai = cx ? p.alpha_im : 0.0;
-            groups[g].push_back(it);
-            costs[g].push_back((double)p.m * p.m * it.ncols + 64.0 * p.m);
+        Item it;
+        it.A = static_cast<const double *>(p.A);
+        it.B = static_cast<double *>(p.B);
+        it.lda = p.lda;
+        it.ldb = p.ldb;
+        it.m = (int32_t)p.m;
+        it.ncols = (int32_t)p.n;
+        it.ar = p.alpha_re;
+        it.ai = cx ? p.alpha_im : 0.0;
+        if (group_is_tiny(g)) {
+            tiny[g].push_back(it);
+            tiny_cost[g].push_back((double)p.m * p.m * p.n + 64.0 * p.m);
+            continue;
+        }
+        const bool azero = it.ar == 0.0 && it.ai == 0.0;
+        std::vector<Item> &b = strips[g][2 * p.m + (azero ? 1 : 0)];
+        for (int64_t c0 = 0; c0 < p.n; c0 += kStripCols) {
+            Item st = it;
+            st.B = it.B + es * c0 * p.ldb;
+            st.ncols = (int32_t)std::min<int64_t>(kStripCols, p.n - c0);
+            b.push_back(st);
         }
     }
-    size_t n_items = 0;
-    for (int g = 0; g < kGroups; ++g) n_items += groups[g].size();
-    img->assign(n_items * sizeof(Item), 0);
-    size_t pos = 0;
+    std::vector<Item> out;
     for (int g = 0; g < kGroups; ++g) {
-        std::vector<size_t> order(groups[g].size());
-        for (size_t i = 0; i < order.size(); ++i) order[i] = i;
-        std::stable_sort(order.begin(), order.end(),
-                         [&](size_t a, size_t b) { return costs[g][a] > costs[g][b]; });
-        t->start[g] = (int)pos;
-        t->count[g] = (int)order.size();
-        for (size_t i : order) {
-            std::memcpy(img->data() + pos * sizeof(Item), &groups[g][i], sizeof(Item));
-            ++pos;
+        t->start[g] = (int)out.size();
+        if (group_is_tiny(g)) {
+            std::vector<size_t> order(tiny[g].size());
+            for (size_t i = 0; i < order.size(); ++i) order[i] = i;
+            std::stable_sort(order.begin(), order.end(),
+                             [&](size_t a, size_t b) { return tiny_cost[g][a] > tiny_cost[g][b]; });
+            for (size_t i : order) out.push_back(tiny[g][i]);
+            t->count[g] = (int)order.size();
+            continue;
         }
+        // Largest m first; within an m, alpha != 0 before alpha == 0 (a
+        // zero fill is short).  Each bucket fills whole wavefronts; the last
+        // one is padded with copies of its final strip that own no columns.
+        int waves = 0;
+        for (int b = 2 * 64 + 1; b >= 0; --b) {
+            const int bb = (b / 2) * 2 + (1 - b % 2);  // 2m before 2m + 1
+            std::vector<Item> &v = strips[g][bb];
+            if (v.empty()) continue;
+            for (const Item &x : v) out.push_back(x);
+            Item pad = v.back();
+            pad.ncols = 0;
+            while ((out.size() - (size_t)t->start[g]) % 4) out.push_back(pad);
+            waves += (int)((v.size() + 3) / 4);
+        }
+        t->count[g] = waves;
     }
+    img->assign(out.size() * sizeof(Item), 0);
+    if (!out.empty()) std::memcpy(img->data(), out.data(), img->size());
 }
 
 // The problems with m > 64: grouped blocked launches for alpha != 0, the
@@ -193,7 +224,7 @@ static hsma_status run_table(const BatchTable &t, hipStream_t s, bool fork = tru
     // when there are several.
     for (int g = 0; g < kGroups; ++g) {
         if (t.count[g] == 0 || !group_is_tiny(g)) continue;
-        const bool cx = g >= 16, unit = (g / 8) % 2;
+        const bool cx = group_cx(g), unit = group_unit(g);
         const void *items = static_cast<const unsigned char *>(t.dev) + (size_t)t.start[g] * sizeof(Item);
         ProfScope prof(HSMA_PHASE_TINY, 0.0, s);
         HSMA_TRY(launch_tiny_group(cx, unit, items, t.count[g], s));
@@ -212,19 +243,17 @@ static hsma_status run_table(const BatchTable &t, hipStream_t s, bool fork = tru
         std::vector<hipEvent_t> joins;
         int k = 0;
         hsma_status st = HSMA_SUCCESS;
-        // Largest-row groups first: they hold the longest items.
+        // Complex groups first: they hold the longest items.
         for (int g = kGroups - 1; g >= 0 && st == HSMA_SUCCESS; --g) {
             if (t.count[g] == 0 || group_is_tiny(g)) continue;
             hipStream_t fs = forking ? pool->fork[k++ % kForkStreams] : s;
             if (fs != s) HSMA_HIP(hipStreamWaitEvent(fs, fork_ev, 0));
-            const bool cx = g >= 16, unit = (g / 8) % 2;
-            const int nch = g % 8 + 1;
+            const bool cx = group_cx(g), unit = group_unit(g);
             const unsigned char *base = static_cast<const unsigned char *>(t.dev);
             const void *items = base + (size_t)t.start[g] * sizeof(Item);
             {
                 ProfScope prof(HSMA_PHASE_SMALL, 0.0, fs);
-                st = cx ? launch_small_group_z(unit, nch, items, t.count[g], fs)
-                        : launch_small_group_d(unit, nch, items, t.count[g], fs);
+                st = launch_strip_group(cx, unit, items, t.count[g], fs);
             }
             if (fs != s) {
                 hipEvent_t j;
@@ -314,7 +343,7 @@ static hsma_status upload(const std::vector<unsigned char> &img, void *dev, hipS
 hsma_status trsm_batched_serial(const hsma_problem *probs, int64_t count, hipStream_t s) {
     HSMA_TRY(check_all(probs, count, nullptr));
     if (count == 0) return HSMA_SUCCESS;
-    if (small_item_bytes_d() != sizeof(Item) || tiny_item_bytes() != sizeof(Item)) return HSMA_NOT_SUPPORTED;
+    if (strip_item_bytes() != sizeof(Item) || tiny_item_bytes() != sizeof(Item)) return HSMA_NOT_SUPPORTED;
     BatchTable t;
     std::vector<unsigned char> img;
     build_image(probs, count, &t, &img);
@@ -343,7 +372,7 @@ hsma_status hsma_trsm_batched(const hsma_problem *probs, int64_t count, int64_t 
     using namespace hsma;
     HSMA_TRY(check_all(probs, count, first_bad));
     if (count == 0) return HSMA_SUCCESS;
-    if (small_item_bytes_d() != sizeof(Item) || tiny_item_bytes() != sizeof(Item)) return HSMA_NOT_SUPPORTED;
+    if (strip_item_bytes() != sizeof(Item) || tiny_item_bytes() != sizeof(Item)) return HSMA_NOT_SUPPORTED;
     hipStream_t s = static_cast<hipStream_t>(stream);
     BatchTable t;
     std::vector<unsigned char> img;
@@ -365,7 +394,7 @@ hsma_status hsma_batch_plan_create(const hsma_problem *probs, int64_t count, int
     if (!plan) return HSMA_INVALID_POINTER;
     *plan = nullptr;
     HSMA_TRY(check_all(probs, count, first_bad));
-    if (small_item_bytes_d() != sizeof(Item) || tiny_item_bytes() != sizeof(Item)) return HSMA_NOT_SUPPORTED;
+    if (strip_item_bytes() != sizeof(Item) || tiny_item_bytes() != sizeof(Item)) return HSMA_NOT_SUPPORTED;
     hsma_batch_plan *p = new hsma_batch_plan();
     std::vector<unsigned char> img;
     build_image(probs, count, &p->table, &img);

@@ -32,9 +32,8 @@ namespace hsma {
 size_t blocked_workspace_bytes(bool cx, int64_t m, int ib);
 int lookup_block_size(bool cx, int64_t m, int64_t n);
 hsma_status upload_async(const void *host, size_t bytes, void *dev, hipStream_t s);
-hsma_status launch_inv_group_d(bool unit, int base, const void *items, int count, hipStream_t s);
-hsma_status launch_inv_group_z(bool unit, int base, const void *items, int count, hipStream_t s);
-size_t inv_item_bytes_d();
+hsma_status launch_inv_group(bool cx, bool unit, int base, const void *items, int count, hipStream_t s);
+size_t inv_item_bytes();
 
 namespace {
 
@@ -183,7 +182,7 @@ Gemm op_gemm(const Prob &p, int pi, const Op &o) {
 // Enqueue every problem (validated; m > 64; alpha != 0) on stream s.
 hsma_status grouped_blocked(const hsma_problem *probs, int64_t count, hipStream_t s) {
     if (count <= 0) return HSMA_SUCCESS;
-    if (inv_item_bytes_d() != sizeof(InvItem)) return HSMA_NOT_SUPPORTED;
+    if (inv_item_bytes() != sizeof(InvItem)) return HSMA_NOT_SUPPORTED;
     std::vector<Prob> ps;
     ps.reserve(count);
     size_t ws_total = 0;
@@ -357,8 +356,7 @@ hsma_status grouped_blocked(const hsma_problem *probs, int64_t count, hipStream_
         const void *d = base + l.img_off;
         if (l.kind == 1) {
             ProfScope prof(HSMA_PHASE_DIAG_INV, 0.0, s);
-            st = l.cx ? launch_inv_group_z(l.unit, l.base, d, l.count, s)
-                      : launch_inv_group_d(l.unit, l.base, d, l.count, s);
+            st = launch_inv_group(l.cx, l.unit, l.base, d, l.count, s);
         } else {
             st = launch_gemm_grouped(l.cx, l.role, l.bm, l.bn, static_cast<const GemmParams *>(d),
                                      l.count, l.tiles, l.flops, s);

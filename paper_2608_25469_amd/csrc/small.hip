@@ -6,14 +6,10 @@
 
 namespace hsma {
 
-hsma_status launch_small_d(bool unit, int m, int64_t n, cplx alpha, const double *A, int64_t lda,
-                           double *B, int64_t ldb, hipStream_t s);
-hsma_status launch_small_z(bool unit, int m, int64_t n, cplx alpha, const double *A, int64_t lda,
-                           double *B, int64_t ldb, hipStream_t s);
-hsma_status launch_inv_base_d(bool unit, int m, int base, int ib, const double *A, int64_t lda,
-                              double *W, hipStream_t s);
-hsma_status launch_inv_base_z(bool unit, int m, int base, int ib, const double *A, int64_t lda,
-                              double *W, hipStream_t s);
+hsma_status launch_strip_one(bool cx, bool unit, int m, int64_t n, cplx alpha, const double *A,
+                             int64_t lda, double *B, int64_t ldb, hipStream_t s);
+hsma_status launch_inv_base(bool cx, bool unit, int m, int base, int ib, const double *A, int64_t lda,
+                            double *W, hipStream_t s);
 
 namespace {
 
@@ -41,8 +37,7 @@ hsma_status launch_small_solve(bool cplx_, bool unit, int m, int64_t n, cplx alp
         return launch_tiny_one(cplx_, unit, m, (int)n, alpha, A, lda, B, ldb, s);
     }
     ProfScope prof(HSMA_PHASE_SMALL, flops, s);
-    return cplx_ ? launch_small_z(unit, m, n, alpha, A, lda, B, ldb, s)
-                 : launch_small_d(unit, m, n, alpha, A, lda, B, ldb, s);
+    return launch_strip_one(cplx_, unit, m, n, alpha, A, lda, B, ldb, s);
 }
 
 hsma_status launch_zero(int64_t m, int64_t n, int es, double *B, int64_t ldb, hipStream_t s) {
@@ -64,8 +59,7 @@ hsma_status launch_diag_inv_base(bool cplx_, bool unit, int m, int base, int ib,
     const int es = cplx_ ? 2 : 1;
     HSMA_TRY(launch_zero((int64_t)ib * ib, nblk, es, W, (int64_t)ib * ib, s));
     ProfScope prof(HSMA_PHASE_DIAG_INV, 0.0, s);
-    return cplx_ ? launch_inv_base_z(unit, m, base, ib, A, lda, W, s)
-                 : launch_inv_base_d(unit, m, base, ib, A, lda, W, s);
+    return launch_inv_base(cplx_, unit, m, base, ib, A, lda, W, s);
 }
 
 }  // namespace hsma

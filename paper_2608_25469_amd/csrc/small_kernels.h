@@ -1,39 +1,25 @@
-// Small-regime TRSM (m <= 64): register-resident forward substitution.
+// Register-resident forward substitution shared by the small-regime kernels.
 //
 // Paper, Sec. 4.2.1: columns of B are independent, so each column is a
-// separate forward substitution; the triangular operand is shared.  Here one
-// 64-lane wavefront owns a panel of up to 64 columns: lane j keeps column j
-// of the panel entirely in VGPRs (y[0..m-1]), so the row-dependency chain runs
-// inside a lane with no synchronisation at all.
+// separate forward substitution; the triangular operand is shared.  Lane j
+// of a 64-lane wavefront keeps column j in VGPRs, so the row-dependency chain
+// runs inside a lane with no synchronisation at all.
 //
-// L is the same for every lane.  Its packed lower triangle is staged once in
-// LDS with direct global-to-LDS loads (no VGPR round trip).  At step k,
-// column k+1 is read from LDS into ceil(m/16) VGPRs laid out so that each
-// 16-lane row of the wavefront holds 16 consecutive rows of the column, and
-// each coefficient reaches all lanes through the 64-bit DPP row_newbcast
-// broadcast with no further memory traffic.  In the left-looking walk the
-// broadcast is the DPP source operand of the multiply-add itself
-// (v_fmac_f64_dpp, dpp_fma.h), so a real update costs one VALU instruction
-// and a complex one four.  The column for the next step is read before the
-// current step's arithmetic, so LDS latency hides behind the dependency
-// chain.
-//
-// The loop nest is fully unrolled for a compile-time row bound MAXM (a
-// multiple of 8) and guarded by the runtime m.  Two walks share this
-// machinery: Panel (right-looking, the whole column live; used with identity
-// right-hand sides to invert diagonal chunks) and PanelLL (left-looking over
-// 16-row blocks, used for general right-hand sides: a lane holds one block
-// at a time, so register use no longer grows with m and larger panels keep
-// two or more wavefronts per SIMD).  Loads of a block are issued before its
-// arithmetic and its rows are stored as soon as they are final, so global
-// traffic overlaps the chain (the load/compute/store overlap of Sec. 4.2.1,
-// Alg. 1, obtained by full unrolling and the hardware's in-order waits).
-//
-// Reciprocals of the diagonal are computed one per lane and broadcast to the
-// whole wave with v_readlane when row k is divided: once per wavefront in the
-// right-looking walk, per 16-row block from the staged panel in the
-// left-looking one (so no separate load of the diagonal precedes the first
-// block).
+// This header holds the DPP broadcast helpers (used here and by the strip
+// kernel of general right-hand sides, strip.hip) and the right-looking Panel
+// walk, which the blocked path uses with identity right-hand sides to invert
+// its diagonal chunks (Sec. 4.3.1): the whole column stays live (y[0..m-1]).
+// L's packed lower triangle is staged once in LDS with direct global-to-LDS
+// loads (no VGPR round trip).  At step k, column k+1 is read from LDS into
+// ceil(m/16) VGPRs laid out so that each 16-lane row of the wavefront holds
+// 16 consecutive rows of the column, and each coefficient reaches all lanes
+// through the 64-bit DPP row_newbcast broadcast with no further memory
+// traffic.  The column for the next step is read before the current step's
+// arithmetic, so LDS latency hides behind the dependency chain.  The loop
+// nest is fully unrolled for a compile-time row bound MAXM (a multiple of 8)
+// and guarded by the runtime m.  Reciprocals of the diagonal are computed one
+// per lane and broadcast to the whole wave with v_readlane when row k is
+// divided.
 
 #pragma once
 
@@ -289,353 +275,15 @@ struct Panel {
     }
 };
 
-// ---------------------------------------------------------------------------
-// The same solve walked left-looking over 16-row blocks (used for general
-// right-hand sides; the identity right-hand sides of the diagonal-block
-// inversion keep the right-looking Panel above).
-//
-// Holding a whole column in registers costs 2 m doubles per lane -- for
-// complex m = 64 all 256 architectural VGPRs, so the compiler spills the
-// working set to AGPRs and only one wavefront fits per SIMD.  Here a lane
-// holds one 16-row block of its column (y) plus one finished block (x):
-// block R is loaded, receives the updates of every finished block K < R
-// (whose final values the same lane stored to B earlier and reloads), solves
-// its own 16 x 16 triangle, and is stored.  Every element still receives its
-// updates -l_ik x_k in ascending k, exactly as in the right-looking order, so
-// the results are the same bit for bit.
-// ---------------------------------------------------------------------------
-template <int B, int E, typename F>
-__device__ __forceinline__ void static_for(F &&f) {
-    if constexpr (B < E) {
-        f(std::integral_constant<int, B>{});
-        static_for<B + 1, E>(f);
-    }
-}
-
-template <bool CX, int MAXM, bool UNIT>
-struct PanelLL {
-    static constexpr int RB = 16;
-    static constexpr int NB = (MAXM + RB - 1) / RB;
-    static constexpr int ES = CX ? 2 : 1;
-    // LDS: the 16-row panel of L that block R needs (rows R*16.., columns
-    // 0..R*16+15), column-major with 16 rows per column.
-    static constexpr int PANEL = RB * MAXM;
-
-    // Coefficients l_{R*16 + l%16, k} of column k for the current panel.
-    static __device__ __forceinline__ void coef(const double *Lp, int lane, int k, double &cr,
-                                                double &ci) {
-        const int e = k * RB + (lane & 15);
-        if (CX) {
-            cr = Lp[2 * e];
-            ci = Lp[2 * e + 1];
-        } else {
-            cr = Lp[e];
-            ci = 0.0;
-        }
-    }
-
-    // Stage rows R*16..R*16+15 of columns 0..(R+1)*16-1 (at most MAXM) with
-    // direct global-to-LDS loads.  Complex: one instruction moves 4 columns
-    // (lane l: column 4c + l/16, row l%16, 16 bytes); real: 2 columns (lane
-    // l: column 2c + l/32, row (l%32)/2, 4-byte half l%2).  Source rows are
-    // clamped to [column, m-1] and columns to m-1, so only the lower triangle
-    // of A is read and nothing outside it; rows and columns beyond m only feed
-    // rows that are never stored, and rows on or above the diagonal are never
-    // used.
-    template <int R>
-    static __device__ __forceinline__ void stage(const double *__restrict__ A, int64_t lda, int m,
-                                                 int lane, double *Lp) {
-        typedef __attribute__((address_space(3))) void lds_void;
-        constexpr int NCOL = ((R + 1) * RB) < MAXM ? ((R + 1) * RB) : MAXM;
-        const int mc = m - 1;
-        if (CX) {
-#pragma unroll
-            for (int c = 0; c < NCOL / 4; ++c) {
-                int col = 4 * c + (lane >> 4);
-                col = col < mc ? col : mc;
-                int row = R * RB + (lane & 15);
-                row = row < col ? col : (row < mc ? row : mc);
-                const double *src = A + 2 * ((int64_t)col * lda + row);
-                __builtin_amdgcn_global_load_lds((const void *)src, (lds_void *)(Lp + 2 * (c * 64)), 16, 0,
-                                                 0);
-            }
-        } else {
-#pragma unroll
-            for (int c = 0; c < NCOL / 2; ++c) {
-                int col = 2 * c + (lane >> 5);
-                col = col < mc ? col : mc;
-                int row = R * RB + ((lane & 31) >> 1);
-                row = row < col ? col : (row < mc ? row : mc);
-                const char *src = reinterpret_cast<const char *>(A + (int64_t)col * lda + row) + 4 * (lane & 1);
-                __builtin_amdgcn_global_load_lds((const void *)src, (lds_void *)(Lp + c * 32), 4, 0, 0);
-            }
-        }
-    }
-
-    // A finished block goes back to B through LDS so that each store
-    // instruction writes four whole 16-row column segments (four 256-byte
-    // runs for complex, 128-byte runs for real) instead of one element of 64
-    // different columns.  Chunk c of LDS holds columns 4c..4c+3, the element
-    // (column 4c + r, row i) in slot 16 (r ^ f) + (i + r + 4 (c % 4)) % 16
-    // with f = (c / 4) % 2: the lanes of a quarter (complex) or half (real)
-    // wavefront then hit distinct LDS banks when they write their rows, and
-    // every read of a chunk is contiguous.
-    static constexpr bool COALESCED_STORE = (MAXM == 64);
-
-    template <int R>
-    static __device__ __forceinline__ void store_block(double *Lp, HSMA_GLOBAL double *__restrict__ Bp,
-                                                       int64_t ldb, int ncols, int m, int lane,
-                                                       const double (&yr)[RB], const double (&yi)[RB]) {
-        __syncthreads();  // the panel's reads are complete
-        {
-            const int c = lane >> 2, r = lane & 3, q = c & 3, f = (c >> 2) & 1;
-#pragma unroll
-            for (int i = 0; i < RB; ++i) {
-                double *p = Lp + ES * (c * 64 + 16 * (r ^ f) + ((i + r + 4 * q) & 15));
-                if (CX) {
-                    p[0] = yr[i];
-                    p[1] = yi[i];
-                } else {
-                    p[0] = yr[i];
-                }
-            }
-        }
-        __syncthreads();  // the block is in LDS
-#pragma unroll
-        for (int c = 0; c < 16; ++c) {
-            const int f = (c >> 2) & 1, q = c & 3;
-            const int r = (lane >> 4) ^ f;
-            const int i = ((lane & 15) - r - 4 * q) & 15;
-            const int col = 4 * c + r;
-            const double *p = Lp + ES * (c * 64 + lane);
-            if (col < ncols && R * RB + i < m) {
-                HSMA_GLOBAL double *dst = Bp + ES * ((int64_t)col * ldb + R * RB + i);
-                if (CX)
-                    *reinterpret_cast<HSMA_GLOBAL dbl2u *>(dst) = dbl2u{p[0], p[1]};
-                else
-                    dst[0] = p[0];
-            }
-        }
-    }
-
-    // Diagonal step KK of block R: x = y[KK] / l_KK, then rows KK+1.. of the
-    // block receive -l_iK x.  c holds column K's coefficients (read one step
-    // earlier); the next column's are read first.  Steps nest so that the
-    // block's row values never pass through a join per step.
-    template <int R, int BR, int KK>
-    static __device__ __forceinline__ void diag_step(const double *Lp, int m, int lane, double rr,
-                                                     double ri, double (&yr)[RB], double (&yi)[RB],
-                                                     double cr, double ci) {
-        if constexpr (KK < BR) {
-            constexpr int K = R * RB + KK;
-            if (K < m) {
-                double nr = 0.0, ni = 0.0;
-                if constexpr (KK + 1 < BR) coef(Lp, lane, K + 1, nr, ni);
-                if (!UNIT) {
-                    const double dr = readlane_d(rr, KK);
-                    if (CX) {
-                        const double di = readlane_d(ri, KK);
-                        const double tr = yr[KK] * dr - yi[KK] * di;
-                        const double ti = yr[KK] * di + yi[KK] * dr;
-                        yr[KK] = tr;
-                        yi[KK] = ti;
-                    } else {
-                        yr[KK] *= dr;
-                    }
-                }
-                const double xr = yr[KK], xi = yi[KK];
-                if constexpr (BR == RB) {
-                    if constexpr (KK + 1 < RB) fnma_rows<CX, KK + 1>(yr, yi, cr, ci, xr, xi);
-                } else {
-                    static_for<KK + 1, BR>([&](auto I) {
-                        constexpr int i = decltype(I)::value;
-                        const double lr = bcast16<i & 15>(cr);
-                        const double li = CX ? bcast16<i & 15>(ci) : 0.0;
-                        fms<CX>(yr[i], yi[i], lr, li, xr, xi);
-                    });
-                }
-                diag_step<R, BR, KK + 1>(Lp, m, lane, rr, ri, yr, yi, nr, ni);
-            }
-        }
-    }
-
-    // Block R: stage its panel of L, load, apply finished blocks, solve the
-    // diagonal triangle, store.
-    template <int R>
-    static __device__ __forceinline__ void block(const double *__restrict__ A, int64_t lda,
-                                                 double *Lp, HSMA_GLOBAL double *__restrict__ bc, bool active,
-                                                 HSMA_GLOBAL double *__restrict__ Bp, int64_t ldb, int ncols,
-                                                 int m, int lane, cplx alpha) {
-        if constexpr (R < NB) {
-            constexpr int BR = (MAXM - R * RB) < RB ? (MAXM - R * RB) : RB;  // rows of this block
-            if (R * RB < m) {
-                __syncthreads();  // the previous panel's reads are complete
-                stage<R>(A, lda, m, lane, Lp);
-                double yr[RB], yi[RB];
-#pragma unroll
-                for (int i = 0; i < BR; ++i) {
-                    const int g = R * RB + i;
-                    const int gc = g < m ? g : m - 1;
-                    if (CX) {
-                        const dbl2u v = reinterpret_cast<const HSMA_GLOBAL dbl2u *>(bc)[gc];
-                        yr[i] = v.x;
-                        yi[i] = v.y;
-                    } else {
-                        yr[i] = bc[gc];
-                        yi[i] = 0.0;
-                    }
-                    if (g >= m) yr[i] = yi[i] = 0.0;
-                }
-                if (alpha.re != 1.0 || alpha.im != 0.0) {
-#pragma unroll
-                    for (int i = 0; i < BR; ++i) {
-                        if (CX) {
-                            const double tr = alpha.re * yr[i] - alpha.im * yi[i];
-                            const double ti = alpha.re * yi[i] + alpha.im * yr[i];
-                            yr[i] = tr;
-                            yi[i] = ti;
-                        } else {
-                            yr[i] *= alpha.re;
-                        }
-                    }
-                }
-                __syncthreads();  // the panel has landed in LDS
-                // Updates from the finished blocks, in ascending column order.
-                static_for<0, R>([&](auto KB) {
-                    constexpr int Kb = decltype(KB)::value;
-                    double xr[RB], xi[RB];
-#pragma unroll
-                    for (int k = 0; k < RB; ++k) {
-                        if (CX) {
-                            const dbl2u v = reinterpret_cast<const HSMA_GLOBAL dbl2u *>(bc)[Kb * RB + k];
-                            xr[k] = v.x;
-                            xi[k] = v.y;
-                        } else {
-                            xr[k] = bc[Kb * RB + k];
-                            xi[k] = 0.0;
-                        }
-                    }
-                    double cr, ci;
-                    coef(Lp, lane, Kb * RB, cr, ci);
-                    static_for<0, RB>([&](auto KK) {
-                        constexpr int kk = decltype(KK)::value;
-                        double nr = 0.0, ni = 0.0;
-                        if constexpr (kk + 1 < RB) coef(Lp, lane, Kb * RB + kk + 1, nr, ni);
-                        if constexpr (BR == RB) {
-                            fnma_rows<CX, 0>(yr, yi, cr, ci, xr[kk], xi[kk]);
-                        } else {
-                            static_for<0, BR>([&](auto I) {
-                                constexpr int i = decltype(I)::value;
-                                const double lr = bcast16<i & 15>(cr);
-                                const double li = CX ? bcast16<i & 15>(ci) : 0.0;
-                                fms<CX>(yr[i], yi[i], lr, li, xr[kk], xi[kk]);
-                            });
-                        }
-                        cr = nr;
-                        ci = ni;
-                    });
-                });
-                // Reciprocals of this block's diagonal, from the staged panel:
-                // lane l holds row R*16 + l%16 (1/d, or conj(d)/|d|^2).
-                double rr = 1.0, ri = 0.0;
-                if (!UNIT && (lane & 15) < BR) {
-                    double vx, vy;
-                    coef(Lp, lane, R * RB + (lane & 15), vx, vy);
-                    if (CX) {
-                        const double den = vx * vx + vy * vy;
-                        rr = vx / den;
-                        ri = -vy / den;
-                    } else {
-                        rr = 1.0 / vx;
-                    }
-                }
-                double cr, ci;
-                coef(Lp, lane, R * RB, cr, ci);
-                diag_step<R, BR, 0>(Lp, m, lane, rr, ri, yr, yi, cr, ci);
-                if constexpr (COALESCED_STORE && BR == RB) {
-                    store_block<R>(Lp, Bp, ldb, ncols, m, lane, yr, yi);
-                } else if (active) {
-#pragma unroll
-                    for (int i = 0; i < BR; ++i) {
-                        if (R * RB + i < m) {
-                            if (CX)
-                                reinterpret_cast<HSMA_GLOBAL dbl2u *>(bc)[R * RB + i] = dbl2u{yr[i], yi[i]};
-                            else
-                                bc[R * RB + i] = yr[i];
-                        }
-                    }
-                }
-                block<R + 1>(A, lda, Lp, bc, active, Bp, ldb, ncols, m, lane, alpha);
-            }
-        }
-    }
-
-    static __device__ __forceinline__ void solve(const double *__restrict__ A, int64_t lda,
-                                                 double *__restrict__ B, int64_t ldb, int m,
-                                                 int ncols, cplx alpha) {
-        // Laundered lane id: see Panel::solve.
-        int lane = threadIdx.x & 63;
-        asm volatile("" : "+v"(lane));
-        const bool active = lane < ncols;
-        HSMA_GLOBAL double *__restrict__ bc = (HSMA_GLOBAL double *)(B + ES * (int64_t)(active ? lane : 0) * ldb);
-        __shared__ double Lp[ES * (COALESCED_STORE && PANEL < RB * 64 ? RB * 64 : PANEL)];
-        block<0>(A, lda, Lp, bc, active, (HSMA_GLOBAL double *)B, ldb, ncols, m, lane, alpha);
-    }
-};
-
-// Work item of the small-solve kernel: one 64-column panel of one problem.
+// Work item of the small-solve kernel (strip.hip): one strip of at most 16
+// columns of one problem.
 struct SmallItem {
     const double *A;
-    double *B;        // first column of the panel
+    double *B;        // first column of the strip
     int64_t lda, ldb; // element units
     int32_t m, ncols;
     double ar, ai;    // alpha
 };
-
-// Device-side descriptor table of a grouped launch: the items of one
-// (dtype, unit) group, one workgroup each.
-struct SmallGroup {
-    const SmallItem *items;
-    int32_t count;
-};
-
-// Single problem (items == nullptr): workgroup b solves panel b of `one`.
-// Grouped (items != nullptr): workgroup b solves item b.  Items are sorted by
-// decreasing cost on the host and the hardware starts workgroups in order as
-// slots free up, so the longest panels start first with no work counter.  (A
-// persistent grid claiming items through an atomic counter was 22 % slower:
-// the claim is one more dependent round trip per item.)
-// Complex panels of 49..64 rows fit two wavefronts per SIMD (256 registers
-// each) with the left-looking walk; without the hint the compiler spreads
-// into the whole register file for one.
-template <bool CX, int NCH>
-constexpr int small_waves() { return (CX && NCH >= 7) ? 2 : 1; }
-
-template <bool CX, int NCH, bool UNIT>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(small_waves<CX, NCH>())))
-void hsma_small_solve(SmallItem one, SmallGroup grp) {
-    const int lane = threadIdx.x & 63;
-    SmallItem d;
-    if (grp.items == nullptr) {
-        const int64_t col0 = (int64_t)blockIdx.x * 64;
-        d = one;
-        d.B = one.B + (CX ? 2 : 1) * col0 * one.ldb;
-        const int64_t left = (int64_t)one.ncols - col0;  // ncols holds n here
-        d.ncols = (int)(left < 64 ? left : 64);
-    } else {
-        if ((int)blockIdx.x >= grp.count) return;
-        d = grp.items[blockIdx.x];
-    }
-    if (d.ar == 0.0 && d.ai == 0.0) {
-        // alpha = 0: B := 0, neither A nor B is read.
-        if (lane < d.ncols) {
-            HSMA_GLOBAL double *bc = (HSMA_GLOBAL double *)(d.B + (CX ? 2 : 1) * (int64_t)lane * d.ldb);
-            for (int i = 0; i < (CX ? 2 : 1) * d.m; ++i) bc[i] = 0.0;
-        }
-        return;
-    }
-    PanelLL<CX, 8 * NCH, UNIT>::solve(d.A, d.lda, d.B, d.ldb, d.m, d.ncols, cplx{d.ar, d.ai});
-}
 
 // Phase 1 of the blocked path (paper Sec. 4.3): the diagonal of L is cut
 // into consecutive chunks of `base` rows (the last one ragged) and every chunk

@@ -176,6 +176,48 @@ def test_leading_dimension_of_L():
             check(L, B, X, 1.0, tag=("lda", m, cx))
 
 
+def _device_at_offset(a, ld, fill=0.0):
+    """a (m x n, Fortran order) in a float64 device buffer whose data start 8
+    bytes in (8-byte, not 16-byte, alignment), leading dimension ld, padding
+    rows filled with `fill`.  Returns (buffer, address of a)."""
+    m, n = a.shape
+    host = np.full((ld, n), fill, dtype=a.dtype, order="F")
+    host[:m] = a
+    flat = np.ascontiguousarray(host.reshape(-1, order="F")).view(np.float64)
+    buf = torch.from_numpy(np.concatenate([[0.0], flat])).to("cuda")
+    return buf, buf.data_ptr() + 8
+
+
+def _read_at_offset(buf, m, n, ld, cx):
+    flat = np.ascontiguousarray(buf.cpu().numpy()[1:])
+    full = (flat.view(np.complex128) if cx else flat).reshape(ld, n, order="F")
+    return np.asfortranarray(full[:m]), np.asfortranarray(full[m:])
+
+
+def test_operands_at_eight_byte_offsets():
+    """L and B 8 bytes into their allocations, with odd leading dimensions:
+    the small path's 16-byte accesses (two real rows, one complex element)
+    must read and write exactly the right elements, and leave B's padding
+    rows alone."""
+    import ctypes
+    for cx in (False, True):
+        for m, n in ((7, 20), (33, 70), (64, 37), (50, 5)):
+            L, B = W.problem(77 + m, m, n, cx)
+            lda = m + 2 if m % 2 else m + 1
+            ldb = m + 2 if m % 2 else m + 3
+            Lbuf, La = _device_at_offset(L, lda)
+            Bbuf, Ba = _device_at_offset(B, ldb, fill=W.PAD_SENTINEL)
+            alpha = complex(0.5, -0.25) if cx else -0.5
+            code = hs.C64F if cx else hs.R64F
+            st = hs.lib().hsma_trsm(hs.NON_UNIT, m, n, hs._alpha_buf(alpha, code), ctypes.c_void_p(La), lda,
+                                    ctypes.c_void_p(Ba), ldb, code, None)
+            assert st == 0, st
+            torch.cuda.synchronize()
+            X, pad = _read_at_offset(Bbuf, m, n, ldb, cx)
+            assert np.all(pad == W.PAD_SENTINEL), (m, n, cx)
+            check(L, B, X, alpha, tag=("offset", m, n, cx))
+
+
 def test_deterministic_repeats():
     for m, ib in ((48, 0), (400, 64)):
         L, B = W.problem(11, m, 100, True)

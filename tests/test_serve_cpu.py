@@ -260,7 +260,7 @@ def test_blocked_classes_split_by_size_and_data_type():
     for (m, n, cx), i in zip(shapes, infos):
         model = fixed + m * m * n * (4.0 if cx else 1.0) / rate
         took = i["t_done_ns"] - i["t_admit_ns"]
-        assert model * 0.999 <= took <= model + 2 * MS, (m, cx, took, model)
+        assert model * 0.999 <= took <= model + 5 * MS, (m, cx, took, model)
 
 
 def exact_pct(v, q):
