@@ -189,7 +189,7 @@ def measured_traffic(name, sources, ok=True):
 
 GEMM_SOURCES = ["paper_2608_25469_amd/csrc/gemm.hip"]
 SMALL_SOURCES = ["paper_2608_25469_amd/csrc/small_kernels.h", "paper_2608_25469_amd/csrc/dpp_fma.h",
-                 "paper_2608_25469_amd/csrc/small_z.hip"]
+                 "paper_2608_25469_amd/csrc/strip.hip"]
 
 
 def time_gpu(fn, steps, warmup, torch):
@@ -314,7 +314,7 @@ def run_single_problem(args, torch, hs, cfg):
         avg = sm["ms"] / max(1, sm["launches"])
         byts = W.algorithmic_bytes(m, n, cx)
         ach = byts / (avg * 1e-3) / 1e9
-        roof = {"bound": "hbm", "kernel": "hsma_small_solve", "achieved": round(ach, 3),
+        roof = {"bound": "hbm", "kernel": "hsma_strip_solve", "achieved": round(ach, 3),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 6),
                 "traffic": None, "avg_launch_ms": avg,
                 "per_unit": "bytes: lower triangle of L once, B read and written once"}
@@ -411,8 +411,8 @@ def run_batched(args, torch, hs, cfg):
     avg_launch_ms = sm["ms"] / max(1, sm["launches"])
     bytes_per_launch = byts_small / launches
     ach = bytes_per_launch / (avg_launch_ms * 1e-3) / 1e9
-    traffic = measured_traffic("small_solve_batched10000_traffic", SMALL_SOURCES, count == cfg["count"])
-    roof = {"bound": "hbm", "kernel": "hsma_small_solve (grouped, one workgroup per item)",
+    traffic = measured_traffic("strip_solve_batched10000_traffic", SMALL_SOURCES, count == cfg["count"])
+    roof = {"bound": "hbm", "kernel": "hsma_strip_solve (grouped: four 16-column strips per wavefront)",
             "achieved": round(ach, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic,
             "avg_launch_ms": avg_launch_ms, "launches_per_step": launches,
@@ -1094,11 +1094,14 @@ def main():
     hs.lib()
 
     if args.calibrate_copy:
-        # A plain device copy of known size (1 GiB read, 1 GiB written): the
-        # reference that rocprofv3's FETCH_SIZE / WRITE_SIZE are scaled by.
+        # Plain kernels of known traffic, the references that rocprofv3's
+        # FETCH_SIZE / WRITE_SIZE are scaled by: a fill (1 GiB written) and
+        # an elementwise dst = src + 1 (1 GiB read, 1 GiB written; ordinary
+        # vector loads, unlike the runtime's copy blit, whose FETCH_SIZE
+        # reads half of what it moves).
         src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
         dst = torch.empty_like(src)
-        dst.copy_(src)
+        torch.add(src, 1.0, out=dst)
         torch.cuda.synchronize()
         del src, dst
 
