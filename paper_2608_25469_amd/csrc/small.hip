@@ -11,6 +11,7 @@ hsma_status launch_strip_one(bool cx, bool unit, int m, int64_t n, cplx alpha, c
 hsma_status launch_inv_base(bool cx, bool unit, int m, int base, int ib, const double *A, int64_t lda,
                             double *W, hipStream_t s);
 
+
 namespace {
 
 // B <- 0 on rows 0..m-1 (es doubles per element).

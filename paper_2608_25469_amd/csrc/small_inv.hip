@@ -65,4 +65,5 @@ hsma_status launch_inv_group(bool cx, bool unit, int base, const void *items, in
 
 size_t inv_item_bytes() { return sizeof(InvItem); }
 
+
 }  // namespace hsma

@@ -38,6 +38,26 @@ __device__ __forceinline__ double readlane_d(double v, int lane) {
     return __hiloint2double(hi, lo);
 }
 
+// Complex product and reciprocal with every rounding fixed (no contraction
+// left to the compiler): the small-solve kernels share them, so the same
+// problem gives the same bits in every kernel that solves it.
+__device__ __forceinline__ void cmul_rn(double ar, double ai, double br, double bi, double &r,
+                                        double &i) {
+    r = __fma_rn(ar, br, -__dmul_rn(ai, bi));
+    i = __fma_rn(ar, bi, __dmul_rn(ai, br));
+}
+// 1/d (real) or conj(d)/|d|^2 (complex).
+__device__ __forceinline__ void recip_rn(bool cx, double dr, double di, double &rr, double &ri) {
+    if (cx) {
+        const double den = __fma_rn(dr, dr, __dmul_rn(di, di));
+        rr = __ddiv_rn(dr, den);
+        ri = -__ddiv_rn(di, den);
+    } else {
+        rr = __ddiv_rn(1.0, dr);
+        ri = 0.0;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Broadcast of L.  Every lane needs every coefficient l_ik (lane j works on
 // column j).  Column k of L is loaded with vector loads into NQ = ceil(MAXM/16)
@@ -148,12 +168,9 @@ struct Panel {
                     const double dr = readlane_d(rr, K);
                     if (CX) {
                         const double di = readlane_d(ri, K);
-                        const double tr = yr[K] * dr - yi[K] * di;
-                        const double ti = yr[K] * di + yi[K] * dr;
-                        yr[K] = tr;
-                        yi[K] = ti;
+                        cmul_rn(yr[K], yi[K], dr, di, yr[K], yi[K]);
                     } else {
-                        yr[K] *= dr;
+                        yr[K] = __dmul_rn(yr[K], dr);
                     }
                 }
                 if constexpr (K + 1 < MAXM) ApplyRows<CX, MAXM, K, K + 1>::run(yr, yi, cr, ci, yr[K], yi[K]);
@@ -181,14 +198,7 @@ struct Panel {
         double rr = 1.0, ri = 0.0;
         if (!UNIT && lane < m) {
             const HSMA_GLOBAL double *d = (const HSMA_GLOBAL double *)(A + ES * ((int64_t)lane + (int64_t)lane * lda));
-            if (CX) {
-                const double vx = d[0], vy = d[1];
-                const double den = vx * vx + vy * vy;
-                rr = vx / den;
-                ri = -vy / den;
-            } else {
-                rr = 1.0 / d[0];
-            }
+            recip_rn(CX, d[0], CX ? d[1] : 0.0, rr, ri);
         }
 
         // Column j of the panel; rows >= m are read at row m-1 and then zeroed.
@@ -213,12 +223,9 @@ struct Panel {
 #pragma unroll
             for (int i = 0; i < MAXM; ++i) {
                 if (CX) {
-                    const double tr = alpha.re * yr[i] - alpha.im * yi[i];
-                    const double ti = alpha.re * yi[i] + alpha.im * yr[i];
-                    yr[i] = tr;
-                    yi[i] = ti;
+                    cmul_rn(alpha.re, alpha.im, yr[i], yi[i], yr[i], yi[i]);
                 } else {
-                    yr[i] *= alpha.re;
+                    yr[i] = __dmul_rn(yr[i], alpha.re);
                 }
             }
         }

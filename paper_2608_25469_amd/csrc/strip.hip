@@ -98,7 +98,7 @@ struct Strip {
     // columns; NQ instructions move the wavefront's 64 columns.  (Two real
     // rows per lane halve the real instructions but measured slower: with
     // odd leading dimensions half of those 16-byte accesses straddle.)
-    static constexpr int RPC = 1;
+    static constexpr int RPC = 1;  // rows per lane and instruction
     static constexpr int LPS = RB / RPC;
     static constexpr int CPI = 64 / LPS;
     static constexpr int NQ = 64 / CPI;
@@ -121,50 +121,42 @@ struct Strip {
         return lane;
     }
 
-    // Chunk of staging instruction Q for rows r0..: this lane's column is
+    // Element of staging instruction Q for rows r0..: this lane's column is
     // (Q * CPI) % 16 + lane / LPS of strip Q * CPI / 16 (the same strip for
     // the whole instruction), its first row r0 + RPC (lane % LPS).  Columns
     // the strip does not own read its column 0; rows are kept below m.
     template <int Q>
-    static __device__ __forceinline__ dbl2u load_chunk(const Strips &S, int lane, int r0, int m) {
+    static __device__ __forceinline__ E load_chunk(const Strips &S, int lane, int r0, int m) {
         constexpr int st = Q * CPI / 16;
         int c = (Q * CPI) % 16 + lane / LPS;
         c = c < S.nc[st] ? c : 0;
         const int row = r0 + RPC * (lane % LPS);
         const HSMA_GLOBAL double *col = S.B[st] + ES * (int64_t)c * S.ldb[st];
-        if constexpr (CX) {
-            return *reinterpret_cast<const HSMA_GLOBAL dbl2u *>(col + 2 * (row < m ? row : m - 1));
-        } else {
-            return dbl2u{col[row < m ? row : m - 1], 0.0};
-        }
+        return *reinterpret_cast<const HSMA_GLOBAL E *>(col + ES * (row < m ? row : m - 1));
     }
-    // The same chunk back to B (owned columns, rows below m).
+    // The same element back to B (owned columns, rows below m).
     template <int Q>
-    static __device__ __forceinline__ void store_chunk(const Strips &S, int lane, int r0, int m, dbl2u v) {
+    static __device__ __forceinline__ void store_chunk(const Strips &S, int lane, int r0, int m, E v) {
         constexpr int st = Q * CPI / 16;
         const int c = (Q * CPI) % 16 + lane / LPS;
         const int row = r0 + RPC * (lane % LPS);
         if (c >= S.nc[st] || row >= m) return;
         HSMA_GLOBAL double *col = (HSMA_GLOBAL double *)S.B[st] + ES * (int64_t)c * S.ldb[st];
-        if constexpr (CX) *reinterpret_cast<HSMA_GLOBAL dbl2u *>(col + 2 * row) = v;
-        else col[row] = v.x;
+        *reinterpret_cast<HSMA_GLOBAL E *>(col + ES * row) = v;
     }
-    // A block's NQ chunks (instruction order), rows r0..r0+RB-1.
-    static __device__ __forceinline__ void load_block(const Strips &S, int lane, int r0, int m, dbl2u (&ch)[NQ]) {
+    // A block's NQ elements per lane (instruction order), rows r0..r0+RB-1.
+    static __device__ __forceinline__ void load_block(const Strips &S, int lane, int r0, int m, E (&ch)[NQ]) {
         const int ln = fresh(lane);
         static_for<0, NQ>([&](auto Q) {
             constexpr int q = decltype(Q)::value;
             ch[q] = load_chunk<q>(S, ln, r0, m);
         });
     }
-    // Instruction-ordered chunks -> LDS; LDS -> this lane's own column.
-    static __device__ __forceinline__ void put(E *lds, int lane, const dbl2u (&ch)[NQ]) {
+    // Instruction-ordered elements -> LDS; LDS -> this lane's own column.
+    static __device__ __forceinline__ void put(E *lds, int lane, const E (&ch)[NQ]) {
         E *p = lds + slot(lane / LPS, RPC * (lane % LPS));
 #pragma unroll
-        for (int q = 0; q < NQ; ++q) {
-            if constexpr (CX) p[q * CPI * CS] = ch[q];
-            else p[q * CPI * CS] = ch[q].x;
-        }
+        for (int q = 0; q < NQ; ++q) p[q * CPI * CS] = ch[q];
     }
     static __device__ __forceinline__ E get(const E *lds, int lane, int k) { return lds[slot(lane, k)]; }
 
@@ -219,12 +211,9 @@ struct Strip {
                     const double dr = bcast16<KK>(rr);
                     if (CX) {
                         const double di = bcast16<KK>(ri);
-                        const double tr = yr[KK] * dr - yi[KK] * di;
-                        const double ti = yr[KK] * di + yi[KK] * dr;
-                        yr[KK] = tr;
-                        yi[KK] = ti;
+                        smallk::cmul_rn(yr[KK], yi[KK], dr, di, yr[KK], yi[KK]);
                     } else {
-                        yr[KK] *= dr;
+                        yr[KK] = __dmul_rn(yr[KK], dr);
                     }
                 }
                 if constexpr (KK + 1 < RB) fnma_rows<CX, KK + 1>(yr, yi, lr, li, yr[KK], yi[KK]);
@@ -252,7 +241,7 @@ struct Strip {
             // diagonal entry, the first stage of finished rows, and the
             // first D coefficient columns (update steps, or diagonal steps
             // when no block is finished).
-            dbl2u ych[NQ];
+            E ych[NQ];
             load_block(S, lane, K0, m, ych);
             double dx = 1.0, dy = 0.0;
             if (!UNIT) ld<CX>(arow + row * ldaE, dx, dy);
@@ -262,7 +251,7 @@ struct Strip {
                 const int kn = K0 + DR + k < m ? K0 + DR + k : m - 1;
                 ld<CX>(arow + kn * ldaE, pr[k], pi[k]);
             }
-            dbl2u xin[NQ];
+            E xin[NQ];
             if (R > 0) load_block(S, lane, 0, m, xin);
             double cr[D], ci[D];
             const HSMA_GLOBAL double *cp = arow;  // coefficient column of the next update step
@@ -285,12 +274,9 @@ struct Strip {
                 if (K0 + i >= m) yr[i] = yi[i] = 0.0;
                 if (scale) {
                     if (CX) {
-                        const double tr = it.ar * yr[i] - it.ai * yi[i];
-                        const double ti = it.ar * yi[i] + it.ai * yr[i];
-                        yr[i] = tr;
-                        yi[i] = ti;
+                        smallk::cmul_rn(it.ar, it.ai, yr[i], yi[i], yr[i], yi[i]);
                     } else {
-                        yr[i] *= it.ar;
+                        yr[i] = __dmul_rn(yr[i], it.ar);
                     }
                 }
             }
@@ -329,15 +315,7 @@ struct Strip {
 
             // Reciprocal of this lane's diagonal entry: 1/d or conj(d)/|d|^2.
             double rr = 1.0, ri = 0.0;
-            if (!UNIT) {
-                if (CX) {
-                    const double den = dx * dx + dy * dy;
-                    rr = dx / den;
-                    ri = -dy / den;
-                } else {
-                    rr = 1.0 / dx;
-                }
-            }
+            if (!UNIT) smallk::recip_rn(CX, dx, dy, rr, ri);
             diag<0>(arow, ldaE, K0, m, rr, ri, yr, yi, cr, ci, pr, pi);
 
             // Back to B through LDS, whole column segments per instruction.
@@ -349,10 +327,7 @@ struct Strip {
                 const E *p = lds + slot(ln / LPS, RPC * (ln % LPS));
                 static_for<0, NQ>([&](auto Q) {
                     constexpr int q = decltype(Q)::value;
-                    dbl2u v;
-                    if constexpr (CX) v = p[q * CPI * CS];
-                    else v = dbl2u{p[q * CPI * CS], 0.0};
-                    store_chunk<q>(S, ln, K0, m, v);
+                    store_chunk<q>(S, ln, K0, m, p[q * CPI * CS]);
                 });
             }
             __builtin_amdgcn_wave_barrier();
