@@ -305,17 +305,31 @@ __global__ __launch_bounds__(256, (occ_for(BM, BN))) void hsma_gemm(const GemmPa
     // walked in groups of 8 tile-rows.
     const int T = p.tiles_m * p.tiles_n;
     const int bid = blockIdx.x;
-    const int nb = gridDim.x;  // multiple of 8
-    const int per = nb / 8;
-    const int t = (bid % 8) * per + bid / 8;
-    if (t >= T) return;
-    constexpr int GROUP = 8;
-    const int gsz_full = GROUP * p.tiles_n;
-    const int g = t / gsz_full;
-    const int first = g * GROUP;
-    const int gsize = (p.tiles_m - first) < GROUP ? (p.tiles_m - first) : GROUP;
-    const int tm = first + (t % gsz_full) % gsize;
-    const int tn = (t % gsz_full) / gsize;
+    int tm, tn;
+    if (p.k_lower || p.c_lower) {
+        // A triangular operand (K bounded by the tile row) or a triangular C
+        // (tiles above the diagonal skipped): a tile row's work grows with
+        // its index, so contiguous runs of rows per XCD would leave the XCD
+        // holding the bottom rows with about twice the average.  Bottom rows
+        // come first instead, and consecutive workgroups (which the hardware
+        // deals out to the XCDs in turn) walk a row, so every XCD gets an
+        // eighth of every row.
+        if (bid >= T) return;
+        tm = p.tiles_m - 1 - bid / p.tiles_n;
+        tn = bid % p.tiles_n;
+    } else {
+        const int nb = gridDim.x;  // multiple of 8
+        const int per = nb / 8;
+        const int t = (bid % 8) * per + bid / 8;
+        if (t >= T) return;
+        constexpr int GROUP = 8;
+        const int gsz_full = GROUP * p.tiles_n;
+        const int g = t / gsz_full;
+        const int first = g * GROUP;
+        const int gsize = (p.tiles_m - first) < GROUP ? (p.tiles_m - first) : GROUP;
+        tm = first + (t % gsz_full) % gsize;
+        tn = (t % gsz_full) / gsize;
+    }
     const int batch = blockIdx.y;
     const int bo = batch / p.inner, bi = batch % p.inner;
     gemm_tile<CX, BM, BN, WM, WN>(p, p.A + bo * p.a_outer + bi * p.a_inner,
