@@ -189,7 +189,7 @@ def measured_traffic(name, sources, ok=True):
 
 GEMM_SOURCES = ["paper_2608_25469_amd/csrc/gemm.hip"]
 SMALL_SOURCES = ["paper_2608_25469_amd/csrc/small_kernels.h", "paper_2608_25469_amd/csrc/dpp_fma.h",
-                 "paper_2608_25469_amd/csrc/strip.hip"]
+                 "paper_2608_25469_amd/csrc/strip.hip", "paper_2608_25469_amd/csrc/batched.cpp"]
 
 
 def time_gpu(fn, steps, warmup, torch):
@@ -402,10 +402,12 @@ def run_batched(args, torch, hs, cfg):
     ev_ms = ev0.elapsed_time(ev1) / args.steps
     fl = b.total_flops()
     byts = b.total_bytes()
-    # The dominant kernel is the small-solve kernel; problems with m, n <= 16
-    # run in the fused kernel's own (short) launch and are left out of its bytes.
+    # The dominant kernel is the strip kernel.  Problems with m, n <= 16 ride
+    # in its launch when the batch has other small problems (else they run in
+    # the fused kernel's own launch, and are left out of its bytes).
     tiny = [(m_, n_) for m_, n_ in b.shapes if m_ <= 16 and n_ <= 16]
-    byts_small = byts - sum(W.algorithmic_bytes(m_, n_, True) for m_, n_ in tiny)
+    tiny_launched = prof["tiny"]["launches"] > 0
+    byts_small = byts - (sum(W.algorithmic_bytes(m_, n_, True) for m_, n_ in tiny) if tiny_launched else 0)
     sm = prof["small"]
     launches = max(1, sm["launches"] // args.steps)
     avg_launch_ms = sm["ms"] / max(1, sm["launches"])
@@ -417,15 +419,17 @@ def run_batched(args, torch, hs, cfg):
             "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic,
             "avg_launch_ms": avg_launch_ms, "launches_per_step": launches,
             "bytes_per_launch": bytes_per_launch, "bytes_per_step": byts,
-            "fused_very_small_problems": len(tiny),
+            "very_small_problems": len(tiny), "very_small_in_strip_launch": not tiny_launched,
             "fused_launch_ms_per_step": prof["tiny"]["ms"] / args.steps,
             "step_ms_events": ev_ms,
             "step_rate_gbs": round(byts / (ev_ms * 1e-3) / 1e9, 2),
             "per_unit": "per problem: 16 (m(m+1)/2 + 2mn) bytes (lower triangle of L once, B read and "
                         "written once); a launch serves one (dtype, diag) group, so bytes per "
                         "launch = bytes of the group's problems (one group here: every problem is "
-                        "complex with a non-unit diagonal; the problems with m, n <= 16 run in the "
-                        "fused kernel's launch and are not counted)"}
+                        "complex with a non-unit diagonal, the ones with m, n <= 16 included as "
+                        "one-strip items)" if not tiny_launched else
+                        "per problem: 16 (m(m+1)/2 + 2mn) bytes; the problems with m, n <= 16 ran in "
+                        "the fused kernel's own launch and are not counted"}
 
     # One-shot API (host descriptors uploaded each call) for reference.
     oneshot_ms = time_gpu(lambda: hs.trsm_batched(probs), max(2, args.steps), 1, torch)

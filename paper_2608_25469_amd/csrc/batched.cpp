@@ -8,7 +8,8 @@
 // a whole wavefront.  Strips are grouped by (data type, diagonal kind); inside
 // a group the wavefronts are ordered by decreasing m (longest processing time
 // first: the hardware starts workgroups in that order).  Problems with m, n
-// <= 16 go to the fused very-small kernel instead.  The descriptor table is
+// <= 16 go to the fused very-small kernel when their group has no strips,
+// and become one-strip items otherwise (the two kernels give the same bits).  The descriptor table is
 // uploaded in one copy; the group launches are forked onto library-owned
 // streams so they overlap on the device, and joined back into the caller's
 // stream.  Problems with m > 64 take the grouped blocked path (grouped.cpp)
@@ -165,6 +166,20 @@ static void build_image(const hsma_problem *probs, int64_t count, BatchTable *t,
             st.ncols = (int32_t)std::min<int64_t>(kStripCols, p.n - c0);
             b.push_back(st);
         }
+    }
+    // When a (data type, diagonal kind) also has strips, its very small
+    // problems join them as one-strip items: one launch instead of two, and
+    // the fused kernel gives the same bits as the strip kernel anyway.
+    for (int g = 0; g < kGroups; g += 2) {
+        bool strips_here = false;
+        for (const std::vector<Item> &b : strips[g + 1]) strips_here = strips_here || !b.empty();
+        if (!strips_here || tiny[g].empty()) continue;
+        for (const Item &x : tiny[g]) {
+            const bool azero = x.ar == 0.0 && x.ai == 0.0;
+            strips[g + 1][2 * x.m + (azero ? 1 : 0)].push_back(x);
+        }
+        tiny[g].clear();
+        tiny_cost[g].clear();
     }
     std::vector<Item> out;
     for (int g = 0; g < kGroups; ++g) {

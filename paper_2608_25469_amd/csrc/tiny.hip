@@ -16,7 +16,7 @@
 // or launch a problem lands in, so a problem gives the same bits alone and
 // in a batch.
 
-#include "internal.h"
+#include "small_kernels.h"
 
 namespace hsma {
 namespace {
@@ -36,6 +36,12 @@ constexpr int kMax = 16;
 template <bool CX>
 constexpr int quarter_stride() { return CX ? 276 : 280; }
 
+// Element operations.  Every rounding is spelled out and in the same order
+// as in the strip kernel's walk (strip.hip, dpp_fma.h): the update of a
+// complex row is yr -= lr xr, yi -= lr xi, yr += li xi, yi -= li xr, each a
+// fused multiply-add; the diagonal is applied as a product with its
+// reciprocal; alpha scales only when it is not 1.  So a problem gives the
+// same bits here as there.
 template <bool CX>
 struct D;
 template <>
@@ -45,10 +51,14 @@ struct D<false> {
     static __device__ __forceinline__ void st(HSMA_GLOBAL double *p, int64_t i, V v) { p[i] = v; }
     static __device__ __forceinline__ V zero() { return 0.0; }
     static __device__ __forceinline__ V one() { return 1.0; }
-    static __device__ __forceinline__ V mul(V a, V b) { return a * b; }
-    static __device__ __forceinline__ V fnms(V acc, V a, V b) { return acc - a * b; }
-    static __device__ __forceinline__ V div(V a, V d) { return a / d; }
-    static __device__ __forceinline__ V make(double r, double) { return r; }
+    static __device__ __forceinline__ void fnms(V &acc, V l, V x) { acc = __fma_rn(-l, x, acc); }
+    static __device__ __forceinline__ V scale(V x, V r) { return __dmul_rn(x, r); }
+    static __device__ __forceinline__ V alpha(V x, double ar, double) { return __dmul_rn(x, ar); }
+    static __device__ __forceinline__ V recip(V d) {
+        double r, i;
+        smallk::recip_rn(false, d, 0.0, r, i);
+        return r;
+    }
 };
 template <>
 struct D<true> {
@@ -61,17 +71,29 @@ struct D<true> {
     }
     static __device__ __forceinline__ V zero() { return V{0.0, 0.0}; }
     static __device__ __forceinline__ V one() { return V{1.0, 0.0}; }
-    static __device__ __forceinline__ V mul(V a, V b) {
-        return V{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+    static __device__ __forceinline__ void fnms(V &acc, V l, V x) {
+        double yr = acc.x, yi = acc.y;
+        yr = __fma_rn(-l.x, x.x, yr);
+        yi = __fma_rn(-l.x, x.y, yi);
+        yr = __fma_rn(l.y, x.y, yr);
+        yi = __fma_rn(-l.y, x.x, yi);
+        acc = V{yr, yi};
     }
-    static __device__ __forceinline__ V fnms(V acc, V a, V b) {
-        return V{acc.x - (a.x * b.x - a.y * b.y), acc.y - (a.x * b.y + a.y * b.x)};
+    static __device__ __forceinline__ V scale(V x, V r) {
+        double a, b;
+        smallk::cmul_rn(x.x, x.y, r.x, r.y, a, b);
+        return V{a, b};
     }
-    static __device__ __forceinline__ V div(V a, V d) {  // a conj(d) / |d|^2
-        const double den = d.x * d.x + d.y * d.y;
-        return V{(a.x * d.x + a.y * d.y) / den, (a.y * d.x - a.x * d.y) / den};
+    static __device__ __forceinline__ V alpha(V x, double ar, double ai) {
+        double a, b;
+        smallk::cmul_rn(ar, ai, x.x, x.y, a, b);
+        return V{a, b};
     }
-    static __device__ __forceinline__ V make(double r, double i) { return V{r, i}; }
+    static __device__ __forceinline__ V recip(V d) {
+        double r, i;
+        smallk::recip_rn(true, d.x, d.y, r, i);
+        return V{r, i};
+    }
 };
 
 // Workgroup b solves items 4b .. 4b + 3 (those below count); with items ==
@@ -89,6 +111,8 @@ __global__ __launch_bounds__(64) void hsma_tiny(TinyItem one, const TinyItem *__
     TinyItem it = one;
     if (items && active) it = items[idx];
     V *L = Ls + q * QS;
+    __shared__ V Rs[4 * kMax];  // reciprocals of each quarter's diagonal
+    V *Rq = Rs + q * kMax;
     // alpha == 0: B <- 0, and neither A nor B is read (A may be null).
     const bool azero = it.ar == 0.0 && (!CX || it.ai == 0.0);
     const int m = (active && !azero) ? it.m : 0;
@@ -106,6 +130,13 @@ __global__ __launch_bounds__(64) void hsma_tiny(TinyItem one, const TinyItem *__
     }
 #pragma unroll
     for (int k = 0; k < kMax; ++k) L[i + k * (kMax + 1)] = lv[k];
+    if (!UNIT) {
+        V d = O::one();
+#pragma unroll
+        for (int k = 0; k < kMax; ++k)
+            if (k == i) d = lv[k];
+        Rq[i] = O::recip(d);
+    }
     __syncthreads();
     if (!active || lane >= it.ncols) return;
     HSMA_GLOBAL double *col = (HSMA_GLOBAL double *)it.B + (CX ? 2 : 1) * (int64_t)lane * it.ldb;
@@ -113,19 +144,20 @@ __global__ __launch_bounds__(64) void hsma_tiny(TinyItem one, const TinyItem *__
         for (int r = 0; r < it.m; ++r) O::st(col, r, O::zero());
         return;
     }
-    const V alpha = O::make(it.ar, it.ai);
     V x[kMax];
 #pragma unroll
     for (int r = 0; r < kMax; ++r) x[r] = r < m ? O::ld(col, r) : O::zero();  // all loads in flight
+    if (it.ar != 1.0 || it.ai != 0.0) {
 #pragma unroll
-    for (int r = 0; r < kMax; ++r) x[r] = O::mul(alpha, x[r]);
+        for (int r = 0; r < kMax; ++r) x[r] = O::alpha(x[r], it.ar, it.ai);
+    }
 #pragma unroll
     for (int k = 0; k < kMax; ++k) {
         if (k < m) {
-            if (!UNIT) x[k] = O::div(x[k], L[k + k * (kMax + 1)]);
+            if (!UNIT) x[k] = O::scale(x[k], Rq[k]);
             const V xk = x[k];
 #pragma unroll
-            for (int r = k + 1; r < kMax; ++r) x[r] = O::fnms(x[r], L[r + k * (kMax + 1)], xk);
+            for (int r = k + 1; r < kMax; ++r) O::fnms(x[r], L[r + k * (kMax + 1)], xk);
         }
     }
 #pragma unroll
