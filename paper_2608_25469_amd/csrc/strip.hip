@@ -86,7 +86,12 @@ struct Strips {
     int nc[4];
 };
 
-template <bool CX, bool UNIT>
+// KEEP: every finished block also stays in LDS (a 16-row block of the 64
+// columns per block, at most three), so the updates read it there instead of
+// from B.  For one problem's call, where a few wavefronts cover the GPU and
+// LDS capacity costs nothing, this takes the reads of B off the critical
+// path; a batch keeps the LDS small for occupancy and reads the rows back.
+template <bool CX, bool UNIT, bool KEEP>
 struct Strip {
     static constexpr int ES = CX ? 2 : 1;
     // Column steps between a coefficient load and its use: one complex step
@@ -226,6 +231,7 @@ struct Strip {
     // this lane's strip, S all four.
     static __device__ __forceinline__ void solve(const SmallItem &it, const Strips &S, int m, int lane) {
         __shared__ E lds[64 * CS];
+        __shared__ E kept[KEEP ? 3 * 64 * CS : 1];
         const int c = lane & 15;
         const HSMA_GLOBAL double *A = (const HSMA_GLOBAL double *)it.A;
         const int64_t ldaE = ES * it.lda;
@@ -252,7 +258,7 @@ struct Strip {
                 ld<CX>(arow + kn * ldaE, pr[k], pi[k]);
             }
             E xin[NQ];
-            if (R > 0) load_block(S, lane, 0, m, xin);
+            if (!KEEP && R > 0) load_block(S, lane, 0, m, xin);
             double cr[D], ci[D];
             const HSMA_GLOBAL double *cp = arow;  // coefficient column of the next update step
 #pragma unroll
@@ -286,17 +292,22 @@ struct Strip {
             // column steps run.
             for (int t = 0; t < R; ++t) {
                 const bool more = t + 1 < R;
-                put(lds, lane, xin);
-                __builtin_amdgcn_wave_barrier();
-                if (more) load_block(S, lane, (t + 1) * RB, m, xin);
-                E xq[2] = {get(lds, lane, 0), get(lds, lane, 1)};
+                const E *xs = lds;
+                if constexpr (KEEP) {
+                    xs = kept + t * 64 * CS;
+                } else {
+                    put(lds, lane, xin);
+                    __builtin_amdgcn_wave_barrier();
+                    if (more) load_block(S, lane, (t + 1) * RB, m, xin);
+                }
+                E xq[2] = {get(xs, lane, 0), get(xs, lane, 1)};
                 static_for<0, RB>([&](auto J) {
                     constexpr int j = decltype(J)::value;
                     constexpr int s = j % D;
                     const double lr = cr[s], li = ci[s];
                     double vr, vi;
                     split(xq[j % 2], vr, vi);
-                    if constexpr (j + 2 < RB) xq[j % 2] = get(lds, lane, j + 2);
+                    if constexpr (j + 2 < RB) xq[j % 2] = get(xs, lane, j + 2);
                     // refill the slot with step j + D (this block or the
                     // next), or with the first diagonal steps; the load is
                     // issued either way, from a selected address (a branch
@@ -318,13 +329,16 @@ struct Strip {
             if (!UNIT) smallk::recip_rn(CX, dx, dy, rr, ri);
             diag<0>(arow, ldaE, K0, m, rr, ri, yr, yi, cr, ci, pr, pi);
 
-            // Back to B through LDS, whole column segments per instruction.
+            // Back to B through LDS, whole column segments per instruction
+            // (with KEEP, through the block's own kept copy).
+            E *out = lds;
+            if constexpr (KEEP) out = R < 3 ? kept + R * 64 * CS : lds;
 #pragma unroll
-            for (int k = 0; k < RB; ++k) lds[slot(lane, k)] = join(yr[k], yi[k]);
+            for (int k = 0; k < RB; ++k) out[slot(lane, k)] = join(yr[k], yi[k]);
             __builtin_amdgcn_wave_barrier();
             {
                 const int ln = fresh(lane);
-                const E *p = lds + slot(ln / LPS, RPC * (ln % LPS));
+                const E *p = out + slot(ln / LPS, RPC * (ln % LPS));
                 static_for<0, NQ>([&](auto Q) {
                     constexpr int q = decltype(Q)::value;
                     store_chunk<q>(S, ln, K0, m, p[q * CPI * CS]);
@@ -342,7 +356,7 @@ struct Strip {
 // whose ncols is 0.  A wavefront's strips either all have alpha = 0 (B <- 0,
 // neither A nor B read) or none has; a single problem never has alpha = 0
 // here (that call is a plain zero fill).
-template <bool CX, bool UNIT>
+template <bool CX, bool UNIT, bool KEEP>
 __global__ __launch_bounds__(64) void hsma_strip_solve(SmallItem one, const SmallItem *__restrict__ rows) {
     // The lane id passes through an empty asm so that the compiler does not
     // derive every unrolled address from it up front.
@@ -385,12 +399,13 @@ __global__ __launch_bounds__(64) void hsma_strip_solve(SmallItem one, const Smal
         S.ldb[q] = (int64_t)(((uint64_t)(uint32_t)lhi << 32) | (uint32_t)llo);
         S.nc[q] = __builtin_amdgcn_readlane(it.ncols, 16 * q);
     }
-    Strip<CX, UNIT>::solve(it, S, m, lane);
+    Strip<CX, UNIT, KEEP>::solve(it, S, m, lane);
 }
 
 template <bool CX, bool UNIT>
 void launch_t(unsigned waves, const SmallItem &one, const SmallItem *rows, hipStream_t s) {
-    hipLaunchKernelGGL((hsma_strip_solve<CX, UNIT>), dim3(waves), dim3(64), 0, s, one, rows);
+    if (rows) hipLaunchKernelGGL((hsma_strip_solve<CX, UNIT, false>), dim3(waves), dim3(64), 0, s, one, rows);
+    else hipLaunchKernelGGL((hsma_strip_solve<CX, UNIT, true>), dim3(waves), dim3(64), 0, s, one, rows);
 }
 
 void launch(bool cx, bool unit, unsigned waves, const SmallItem &one, const SmallItem *rows,
