@@ -65,8 +65,10 @@ hsma_status current(Cache **c) {
 // Lock held.
 void trim(Cache &c) {
     for (auto &kv : c.idle) {
-        (void)hipEventSynchronize(kv.second.ev);
-        (void)hipEventDestroy(kv.second.ev);
+        if (kv.second.ev) {
+            (void)hipEventSynchronize(kv.second.ev);
+            (void)hipEventDestroy(kv.second.ev);
+        }
         (void)hipFree(kv.second.p);
         c.held -= kv.first;
     }
@@ -93,13 +95,14 @@ hsma_status ws_alloc(void **p, size_t bytes, hipStream_t s) {
     const size_t b = bin_size(bytes);
     std::lock_guard<std::mutex> lk(c->mu);
     // Best fit among idle blocks of at most twice the bin: the smallest
-    // size present, preferring one freed on this stream.
+    // size present, preferring one usable at once (freed on this stream, or
+    // known idle).
     auto pick = c->idle.end();
     int seen = 0;
     for (auto it = c->idle.lower_bound(b); it != c->idle.end() && it->first <= 2 * b && seen < 16;
          ++it, ++seen) {
         if (pick != c->idle.end() && it->first != pick->first) break;
-        if (it->second.s == s) {
+        if (it->second.s == s || !it->second.ev) {  // usable at once
             pick = it;
             break;
         }
@@ -109,14 +112,14 @@ hsma_status ws_alloc(void **p, size_t bytes, hipStream_t s) {
         const size_t got = pick->first;
         Idle blk = pick->second;
         c->idle.erase(pick);
-        if (blk.s != s) {
+        if (blk.ev && blk.s != s) {
             const hipError_t e = hipStreamWaitEvent(s, blk.ev, 0);
             if (e != hipSuccess) {
                 c->idle.emplace(got, blk);
                 return hip_fail(e);
             }
         }
-        (void)hipEventDestroy(blk.ev);
+        if (blk.ev) (void)hipEventDestroy(blk.ev);
         c->live[blk.p] = got;
         *p = blk.p;
         return HSMA_SUCCESS;
@@ -162,6 +165,24 @@ hsma_status ws_free(void *p, hipStream_t s) {
         return hip_fail(e);
     }
     c->idle.emplace(b, Idle{p, s, ev});
+    return HSMA_SUCCESS;
+}
+
+// A block whose last use is known to have completed on the device (the
+// caller has seen the completion of all work that touched it): it is
+// reusable on any stream at once, with no event.  An event recorded now on
+// the stream that used it would also cover everything enqueued there since,
+// and make the next user wait for that unrelated work.
+hsma_status ws_free_idle(void *p) {
+    if (!p) return HSMA_SUCCESS;
+    Cache *c;
+    HSMA_TRY(current(&c));
+    std::lock_guard<std::mutex> lk(c->mu);
+    auto it = c->live.find(p);
+    if (it == c->live.end()) return HSMA_INVALID_POINTER;
+    const size_t b = it->second;
+    c->live.erase(it);
+    c->idle.emplace(b, Idle{p, nullptr, nullptr});
     return HSMA_SUCCESS;
 }
 

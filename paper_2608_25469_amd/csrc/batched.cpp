@@ -63,7 +63,10 @@ bool group_unit(int g) { return (g / 2) % 2 == 1; }
 constexpr int kStripCols = 16;
 
 struct DevicePool {
-    bool init = false;
+    // Created on the first forking call only: a process that never forks
+    // (the serving queue runs batches serially on its own streams) keeps
+    // every stream it has on a hardware queue of its own.
+    bool forks_made = false;
     hipStream_t fork[kForkStreams] = {};
     std::mutex mu;
     // Pinned staging buffers for descriptor uploads.  A buffer is reusable
@@ -84,14 +87,17 @@ DevicePool g_pools[64];
 hsma_status pool_for(DevicePool **out) {
     DeviceInfo di;
     HSMA_TRY(device_info(&di));
-    DevicePool &p = g_pools[di.device];
-    std::lock_guard<std::mutex> lk(p.mu);
-    if (!p.init) {
+    *out = &g_pools[di.device];
+    return HSMA_SUCCESS;
+}
+
+hsma_status fork_streams(DevicePool *p) {
+    std::lock_guard<std::mutex> lk(p->mu);
+    if (!p->forks_made) {
         for (int i = 0; i < kForkStreams; ++i)
-            HSMA_HIP(hipStreamCreateWithFlags(&p.fork[i], hipStreamNonBlocking));
-        p.init = true;
+            HSMA_HIP(hipStreamCreateWithFlags(&p->fork[i], hipStreamNonBlocking));
+        p->forks_made = true;
     }
-    *out = &p;
     return HSMA_SUCCESS;
 }
 
@@ -250,6 +256,7 @@ static hsma_status run_table(const BatchTable &t, hipStream_t s, bool fork = tru
     if (ngroups > 0) {
         // One launch (or no fork) stays on s: no events.
         const bool forking = fork && ngroups > 1;
+        if (forking) HSMA_TRY(fork_streams(pool));
         hipEvent_t fork_ev = nullptr;
         if (forking) {
             HSMA_HIP(hipEventCreateWithFlags(&fork_ev, hipEventDisableTiming));

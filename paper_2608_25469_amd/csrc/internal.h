@@ -77,6 +77,9 @@ class ProfScope {
 // enqueued on s.
 hsma_status ws_alloc(void **p, size_t bytes, hipStream_t s);
 hsma_status ws_free(void *p, hipStream_t s);
+// Return a block whose last use has completed on the device: reusable on any
+// stream at once (no event).
+hsma_status ws_free_idle(void *p);
 size_t ws_cached_bytes();
 
 // ---------------------------------------------------------------------------

@@ -52,6 +52,10 @@ double clock_ns() {
 enum State { PENDING = 0, RUNNING = 1, DONE = 2, FAILED = 3 };
 
 constexpr size_t kSmallShare = 4096;  // descriptor share of a small request
+#ifndef HSMA_SMALL_CU_STRIDE
+#define HSMA_SMALL_CU_STRIDE 16
+#endif
+constexpr int kSmallCuStride = HSMA_SMALL_CU_STRIDE;  // every k-th CU serves the small class
 
 size_t data_bytes(const hsma_problem &p) {
     const size_t es = p.dtype == HSMA_C64F ? 16 : 8;
@@ -153,17 +157,18 @@ int latency_class(int64_t m) { return m <= 64 ? 0 : (m <= 512 ? 1 : 2); }
 struct hsma_queue {
     hsma_queue_config cfg{};
     std::mutex mu;
-    std::condition_variable cv_sched, cv_done;
+    std::condition_variable cv_sched, cv_done, cv_retire;
     std::deque<hsma::Req *> pending;
     std::unordered_map<uint64_t, hsma::Req *> all;
     std::vector<hsma::Inflight> inflight;
     uint64_t next_ticket = 1;
     size_t budget_used = 0, budget_peak = 0;
     int64_t n_inflight = 0;
-    bool closing = false, stopped = false;
-    std::thread sched;
+    bool closing = false, stopped = false, retire_stop = false;
+    std::thread sched, retire;
     int device = 0;
     hipStream_t small_stream = nullptr;
+    bool cu_reserved = false;  // small class on CUs of its own (CU-masked streams)
     std::vector<hipStream_t> streams;
     size_t rr = 0;
     std::vector<double> sim_free_at;  // simulation: per-stream busy-until (last = small)
@@ -195,13 +200,20 @@ void release_mem(hsma_queue *q, Req *r) {
     }
 }
 
-// Issue the queued frees; takes and releases the lock itself.
+// Issue the queued frees; takes and releases the lock itself.  Every
+// queued block belongs to finished requests (their completion events have
+// fired), so it goes back as idle: an event recorded now on its stream
+// would also cover the later rounds enqueued there, and the next request to
+// reuse the block would wait for them.
 void free_deferred(hsma_queue *q, std::unique_lock<std::mutex> &lk) {
     if (q->deferred.empty()) return;
     std::vector<std::pair<void *, hipStream_t>> fr;
     fr.swap(q->deferred);
     lk.unlock();
-    for (auto &f : fr) (void)ws_free(f.first, f.second);
+    for (auto &f : fr) {
+        if (q->cfg.backend == HSMA_BACKEND_HIP) (void)ws_free_idle(f.first);
+        else (void)ws_free(f.first, f.second);
+    }
     lk.lock();
 }
 
@@ -371,12 +383,14 @@ void launch_simulated(hsma_queue *q, std::vector<Req *> &adm) {
     }
 }
 
-void scheduler(hsma_queue *q) {
+// Retires finished work on a thread of its own, so that a completion is
+// seen (and timed, and its budget returned) within a poll interval, not
+// after the scheduler's current round of launches.
+void retirer(hsma_queue *q) {
     const bool hip = q->cfg.backend == HSMA_BACKEND_HIP;
     if (hip) (void)hipSetDevice(q->device);
     std::unique_lock<std::mutex> lk(q->mu);
-    for (;;) {
-        // 1. completions
+    while (!q->retire_stop) {
         const double t = clock_ns();
         bool retired = false;
         for (size_t i = 0; i < q->inflight.size();) {
@@ -404,7 +418,25 @@ void scheduler(hsma_queue *q) {
                 ++i;
             }
         }
-        if (retired) q->cv_done.notify_all();
+        if (retired) {
+            q->cv_done.notify_all();
+            q->cv_sched.notify_one();  // budget and in-flight slots were returned
+            free_deferred(q, lk);
+        }
+        if (q->inflight.empty())
+            q->cv_retire.wait_for(lk, std::chrono::milliseconds(5));
+        else
+            q->cv_retire.wait_for(lk, std::chrono::microseconds(q->cfg.poll_us));
+    }
+}
+
+void scheduler(hsma_queue *q) {
+    const bool hip = q->cfg.backend == HSMA_BACKEND_HIP;
+    if (hip) (void)hipSetDevice(q->device);
+    std::unique_lock<std::mutex> lk(q->mu);
+    for (;;) {
+        const double t = clock_ns();
+        // 1. completions are the retirer's (above)
         free_deferred(q, lk);
         // 2. admission, strictly in arrival order
         std::vector<Req *> adm;
@@ -430,6 +462,7 @@ void scheduler(hsma_queue *q) {
             lk.lock();
             q->rounds++;
             q->launch_ns += t1 - t0;
+            q->cv_retire.notify_one();
             continue;
         }
         if (q->closing && q->inflight.empty()) {
@@ -443,11 +476,8 @@ void scheduler(hsma_queue *q) {
             }
             break;
         }
-        // 3. nothing to launch: wait for arrivals or releases, or poll
-        if (q->inflight.empty())
-            q->cv_sched.wait_for(lk, std::chrono::milliseconds(5));
-        else
-            q->cv_sched.wait_for(lk, std::chrono::microseconds(q->cfg.poll_us));
+        // 3. nothing to launch: wait for arrivals, releases or retirements
+        q->cv_sched.wait_for(lk, std::chrono::milliseconds(q->inflight.empty() ? 5 : 1));
     }
     q->stopped = true;
     q->cv_done.notify_all();
@@ -511,11 +541,44 @@ hsma_status hsma_queue_create(const hsma_queue_config *cfg, hsma_queue **out) {
     q->cfg = c;
     if (c.backend == HSMA_BACKEND_HIP) {
         hipError_t e = hipGetDevice(&q->device);
-        if (e == hipSuccess) e = hipStreamCreateWithFlags(&q->small_stream, hipStreamNonBlocking);
-        for (int i = 0; e == hipSuccess && i < c.n_streams; ++i) {
-            hipStream_t s;
-            e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
-            if (e == hipSuccess) q->streams.push_back(s);
+        // The small class's stream gets one CU in sixteen to itself and the
+        // blocked classes' streams the rest.  A blocked round's products fill
+        // every CU with workgroups that run for hundreds of microseconds; a
+        // small request's few wavefronts would otherwise wait for a free slot
+        // behind them.
+        int ncu = 0;
+        if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, q->device);
+        std::vector<uint32_t> small_mask, big_mask;
+        if (e == hipSuccess && ncu >= 64 && kSmallCuStride > 1) {
+            small_mask.assign((size_t)(ncu + 31) / 32, 0u);
+            big_mask.assign(small_mask.size(), 0u);
+            for (int cu = 0; cu < ncu; ++cu)
+                ((cu % kSmallCuStride == 0) ? small_mask : big_mask)[cu / 32] |= 1u << (cu % 32);
+        }
+        // Each CU-masked stream takes a hardware queue of its own; where the
+        // process has too few (GPU_MAX_HW_QUEUES), plain streams are used.
+        auto make_all = [&](bool masked) {
+            hipError_t r = masked ? hipExtStreamCreateWithCUMask(&q->small_stream, (uint32_t)small_mask.size(),
+                                                                 small_mask.data())
+                                  : hipStreamCreateWithFlags(&q->small_stream, hipStreamNonBlocking);
+            for (int i = 0; r == hipSuccess && i < c.n_streams; ++i) {
+                hipStream_t s;
+                r = masked ? hipExtStreamCreateWithCUMask(&s, (uint32_t)big_mask.size(), big_mask.data())
+                           : hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+                if (r == hipSuccess) q->streams.push_back(s);
+            }
+            if (r != hipSuccess) {
+                for (auto s : q->streams) (void)hipStreamDestroy(s);
+                q->streams.clear();
+                if (q->small_stream) (void)hipStreamDestroy(q->small_stream);
+                q->small_stream = nullptr;
+                (void)hipGetLastError();
+            }
+            return r;
+        };
+        if (e == hipSuccess) {
+            q->cu_reserved = !small_mask.empty() && make_all(true) == hipSuccess;
+            if (!q->cu_reserved) e = make_all(false);
         }
         if (e != hipSuccess) {
             for (auto s : q->streams) (void)hipStreamDestroy(s);
@@ -527,6 +590,7 @@ hsma_status hsma_queue_create(const hsma_queue_config *cfg, hsma_queue **out) {
         q->sim_free_at.assign((size_t)c.n_streams + 1, 0.0);
     }
     q->sched = std::thread(scheduler, q);
+    q->retire = std::thread(retirer, q);
     *out = q;
     return HSMA_SUCCESS;
 }
@@ -686,6 +750,12 @@ hsma_status hsma_queue_destroy(hsma_queue *q) {
     }
     q->cv_sched.notify_one();
     if (q->sched.joinable()) q->sched.join();
+    {
+        std::lock_guard<std::mutex> lk(q->mu);
+        q->retire_stop = true;
+    }
+    q->cv_retire.notify_one();
+    if (q->retire.joinable()) q->retire.join();
     {
         std::unique_lock<std::mutex> lk(q->mu);
         for (auto &kv : q->all) {
