@@ -250,35 +250,64 @@ def from_colmajor(t) -> np.ndarray:
 
 def leading_dim(t) -> int:
     m, n = t.shape
-    if t.stride(0) != 1 and m > 1:
+    s0, s1 = t.stride()
+    if s0 != 1 and m > 1:
         raise ValueError("matrix must be column-major (stride(0) == 1)")
     if n <= 1:
-        return max(1, m) if t.stride(1) < m else t.stride(1)
-    return t.stride(1)
+        return max(1, m) if s1 < m else s1
+    return s1
+
+
+_DTYPE_CODES = None
 
 
 def _dtype_code(t) -> int:
-    torch = _torch()
-    codes = {torch.float64: R64F, torch.complex128: C64F, torch.float32: R32F,
-             torch.complex64: C32F}
-    if t.dtype in codes:
-        return codes[t.dtype]
-    raise TypeError("tensors must be float64, complex128, float32 or complex64")
+    global _DTYPE_CODES
+    if _DTYPE_CODES is None:
+        torch = _torch()
+        _DTYPE_CODES = {torch.float64: R64F, torch.complex128: C64F, torch.float32: R32F,
+                        torch.complex64: C32F}
+    code = _DTYPE_CODES.get(t.dtype)
+    if code is None:
+        raise TypeError("tensors must be float64, complex128, float32 or complex64")
+    return code
+
+
+# Host scalars of nonzero real Python numbers, shared between calls: the
+# library copies alpha before it returns, so a buffer is only ever read.
+# (Zeros are not cached: -0.0 and 0.0 are one dictionary key.)
+_ALPHA_BUFS: dict = {}
 
 
 def _alpha_buf(alpha, code):
     """Host scalar of the data type: double[2] for FP64, float[2] for FP32."""
+    plain = type(alpha) in (float, int) and alpha != 0
+    if plain:
+        buf = _ALPHA_BUFS.get((alpha, type(alpha), code))
+        if buf is not None:
+            return buf
     a = complex(alpha)
     if code in (R64F, R32F) and a.imag != 0:
         raise ValueError("complex alpha for a real problem")
     if code in (R32F, C32F):
-        return (ctypes.c_float * 2)(a.real, a.imag)
-    return (ctypes.c_double * 2)(a.real, a.imag)
+        buf = (ctypes.c_float * 2)(a.real, a.imag)
+    else:
+        buf = (ctypes.c_double * 2)(a.real, a.imag)
+    if plain:
+        if len(_ALPHA_BUFS) >= 256:
+            _ALPHA_BUFS.clear()
+        _ALPHA_BUFS[(alpha, type(alpha), code)] = buf
+    return buf
 
 
 def _stream_handle(stream) -> int:
     torch = _torch()
     if stream is None:
+        # torch's current stream on the current device, without building a
+        # Stream object per call
+        raw = getattr(torch._C, "_cuda_getCurrentRawStream", None)
+        if raw is not None:
+            return raw(torch.cuda.current_device())
         return torch.cuda.current_stream().cuda_stream
     if isinstance(stream, int):
         return stream
@@ -312,6 +341,14 @@ def trsm(L, B, alpha=1.0, unit: bool = False, block_size: int = 0, path: int = 0
         raise ValueError("L must be m x m")
     if m and n and (not L.is_cuda or not B.is_cuda):
         raise ValueError("tensors must be on the GPU")
+    if not (block_size or path or report or mixed or refine_steps or backward_error
+            or refine_tol or graph):
+        # A plain solve: the options-free entry point, nothing built per call.
+        st = lib().hsma_trsm(UNIT if unit else NON_UNIT, m, n, _alpha_buf(alpha, code),
+                             L.data_ptr(), leading_dim(L), B.data_ptr(), leading_dim(B), code,
+                             _stream_handle(stream))
+        _check(st, "hsma_trsm")
+        return B
     opts = TrsmOptions(block_size, path, PREC_MIXED if mixed else PREC_FP64, refine_steps,
                        1 if backward_error else 0, 1 if graph else 0, (ctypes.c_int32 * 2)(),
                        refine_tol)
