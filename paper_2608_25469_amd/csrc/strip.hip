@@ -86,12 +86,15 @@ struct Strips {
     int nc[4];
 };
 
-// KEEP: every finished block also stays in LDS (a 16-row block of the 64
-// columns per block, at most three), so the updates read it there instead of
-// from B.  For one problem's call, where a few wavefronts cover the GPU and
-// LDS capacity costs nothing, this takes the reads of B off the critical
-// path; a batch keeps the LDS small for occupancy and reads the rows back.
-template <bool CX, bool UNIT, bool KEEP>
+// NK: the last NK finished blocks also stay in LDS (a 16-row block of the
+// 64 columns each, in a ring of NK slots), so the updates read them there
+// instead of from B; older blocks are read back from B.  With NK = 3 no row
+// is ever read back (m <= 64 has at most four blocks).  For one problem's
+// call, where a few wavefronts cover the GPU and LDS capacity costs nothing,
+// NK = 3 takes the reads of B off the critical path.  In a batch each kept
+// block costs occupancy (LDS per wavefront) but saves re-reads that mostly
+// miss L2 by the time they come: the launcher picks NK per data type.
+template <bool CX, bool UNIT, int NK>
 struct Strip {
     static constexpr int ES = CX ? 2 : 1;
     // Column steps between a coefficient load and its use: one complex step
@@ -231,7 +234,7 @@ struct Strip {
     // this lane's strip, S all four.
     static __device__ __forceinline__ void solve(const SmallItem &it, const Strips &S, int m, int lane) {
         __shared__ E lds[64 * CS];
-        __shared__ E kept[KEEP ? 3 * 64 * CS : 1];
+        __shared__ E kept[NK > 0 ? NK * 64 * CS : 1];
         const int c = lane & 15;
         const HSMA_GLOBAL double *A = (const HSMA_GLOBAL double *)it.A;
         const int64_t ldaE = ES * it.lda;
@@ -258,7 +261,10 @@ struct Strip {
                 ld<CX>(arow + kn * ldaE, pr[k], pi[k]);
             }
             E xin[NQ];
-            if (!KEEP && R > 0) load_block(S, lane, 0, m, xin);
+            // finished blocks t < R - NK come back from B, t = 0 first
+            // (none with NK >= 3: m <= 64 has at most four blocks)
+            const int nread = (NK >= 3 || R <= NK) ? 0 : R - NK;
+            if (nread > 0) load_block(S, lane, 0, m, xin);
             double cr[D], ci[D];
             const HSMA_GLOBAL double *cp = arow;  // coefficient column of the next update step
 #pragma unroll
@@ -293,12 +299,12 @@ struct Strip {
             for (int t = 0; t < R; ++t) {
                 const bool more = t + 1 < R;
                 const E *xs = lds;
-                if constexpr (KEEP) {
-                    xs = kept + t * 64 * CS;
+                if (t >= nread) {
+                    xs = kept + (t % (NK > 0 ? NK : 1)) * 64 * CS;
                 } else {
                     put(lds, lane, xin);
                     __builtin_amdgcn_wave_barrier();
-                    if (more) load_block(S, lane, (t + 1) * RB, m, xin);
+                    if (t + 1 < nread) load_block(S, lane, (t + 1) * RB, m, xin);
                 }
                 E xq[2] = {get(xs, lane, 0), get(xs, lane, 1)};
                 static_for<0, RB>([&](auto J) {
@@ -330,9 +336,9 @@ struct Strip {
             diag<0>(arow, ldaE, K0, m, rr, ri, yr, yi, cr, ci, pr, pi);
 
             // Back to B through LDS, whole column segments per instruction
-            // (with KEEP, through the block's own kept copy).
+            // (through the block's kept slot when a later block will read it).
             E *out = lds;
-            if constexpr (KEEP) out = R < 3 ? kept + R * 64 * CS : lds;
+            if constexpr (NK > 0) out = R + 1 < nb ? kept + (R % NK) * 64 * CS : lds;
 #pragma unroll
             for (int k = 0; k < RB; ++k) out[slot(lane, k)] = join(yr[k], yi[k]);
             __builtin_amdgcn_wave_barrier();
@@ -356,7 +362,7 @@ struct Strip {
 // whose ncols is 0.  A wavefront's strips either all have alpha = 0 (B <- 0,
 // neither A nor B read) or none has; a single problem never has alpha = 0
 // here (that call is a plain zero fill).
-template <bool CX, bool UNIT, bool KEEP>
+template <bool CX, bool UNIT, int NK>
 __global__ __launch_bounds__(64) void hsma_strip_solve(SmallItem one, const SmallItem *__restrict__ rows) {
     // The lane id passes through an empty asm so that the compiler does not
     // derive every unrolled address from it up front.
@@ -399,13 +405,25 @@ __global__ __launch_bounds__(64) void hsma_strip_solve(SmallItem one, const Smal
         S.ldb[q] = (int64_t)(((uint64_t)(uint32_t)lhi << 32) | (uint32_t)llo);
         S.nc[q] = __builtin_amdgcn_readlane(it.ncols, 16 * q);
     }
-    Strip<CX, UNIT, KEEP>::solve(it, S, m, lane);
+    Strip<CX, UNIT, NK>::solve(it, S, m, lane);
 }
+
+// Finished blocks a batch keeps in LDS per wavefront (compile-time
+// tunables).  Real data keeps two (8.5 KB each beside the 8.5 KB stage: six
+// wavefronts per CU); complex keeps none, as any kept block (17 KB) would
+// halve the eight wavefronts per CU that its registers allow.
+#ifndef HSMA_STRIP_BATCH_KEEP_CX
+#define HSMA_STRIP_BATCH_KEEP_CX 0
+#endif
+#ifndef HSMA_STRIP_BATCH_KEEP_R
+#define HSMA_STRIP_BATCH_KEEP_R 2
+#endif
 
 template <bool CX, bool UNIT>
 void launch_t(unsigned waves, const SmallItem &one, const SmallItem *rows, hipStream_t s) {
-    if (rows) hipLaunchKernelGGL((hsma_strip_solve<CX, UNIT, false>), dim3(waves), dim3(64), 0, s, one, rows);
-    else hipLaunchKernelGGL((hsma_strip_solve<CX, UNIT, true>), dim3(waves), dim3(64), 0, s, one, rows);
+    constexpr int NKB = CX ? HSMA_STRIP_BATCH_KEEP_CX : HSMA_STRIP_BATCH_KEEP_R;
+    if (rows) hipLaunchKernelGGL((hsma_strip_solve<CX, UNIT, NKB>), dim3(waves), dim3(64), 0, s, one, rows);
+    else hipLaunchKernelGGL((hsma_strip_solve<CX, UNIT, 3>), dim3(waves), dim3(64), 0, s, one, rows);
 }
 
 void launch(bool cx, bool unit, unsigned waves, const SmallItem &one, const SmallItem *rows,
