@@ -21,6 +21,7 @@
 #include <vector>
 
 #include "internal.h"
+#include "strip_pack.h"
 
 namespace hsma {
 
@@ -140,11 +141,8 @@ static void build_image(const hsma_problem *probs, int64_t count, BatchTable *t,
     std::vector<double> tiny_cost[kGroups];
     // Strips, bucketed per group by (m, alpha == 0): bucket 2 m + azero, in
     // problem order, with each problem's span (first strip, strip count).
-    struct Span {
-        int first, k;
-    };
     std::vector<Item> strips[kGroups][2 * 65];
-    std::vector<Span> spans[kGroups][2 * 65];
+    std::vector<StripSpan> spans[kGroups][2 * 65];
     for (int64_t i = 0; i < count; ++i) {
         const hsma_problem &p = probs[i];
         if (p.m == 0 || p.n == 0) continue;
@@ -179,7 +177,7 @@ static void build_image(const hsma_problem *probs, int64_t count, BatchTable *t,
             st.ncols = (int32_t)std::min<int64_t>(kStripCols, p.n - c0);
             b.push_back(st);
         }
-        spans[g][bk].push_back(Span{first, (int)b.size() - first});
+        spans[g][bk].push_back(StripSpan{first, (int)b.size() - first});
     }
     // When a (data type, diagonal kind) also has strips, its very small
     // problems join them as one-strip items: one launch instead of two, and
@@ -191,7 +189,7 @@ static void build_image(const hsma_problem *probs, int64_t count, BatchTable *t,
         for (const Item &x : tiny[g]) {
             const bool azero = x.ar == 0.0 && x.ai == 0.0;
             const int bk = 2 * x.m + (azero ? 1 : 0);
-            spans[g + 1][bk].push_back(Span{(int)strips[g + 1][bk].size(), 1});
+            spans[g + 1][bk].push_back(StripSpan{(int)strips[g + 1][bk].size(), 1});
             strips[g + 1][bk].push_back(x);
         }
         tiny[g].clear();
@@ -213,49 +211,14 @@ static void build_image(const hsma_problem *probs, int64_t count, BatchTable *t,
         // zero fill is short).  Each bucket fills whole wavefronts; the last
         // one is padded with copies of its final strip that own no columns.
         //
-        // The strips of one problem in one wavefront read L through the same
-        // loads (equal addresses in one instruction), while a problem split
-        // over two wavefronts has its L read twice.  So a bucket first gives
-        // each problem's first 4 floor(k / 4) strips whole wavefronts, then
-        // fills wavefronts with the remainders (k mod 4 strips, 1..3) whose
-        // sizes add up to four (3 + 1; 2 + 2; 2 + 1 + 1; 1 + 1 + 1 + 1), and
-        // the remainders left over follow one another: no more wavefronts
-        // than packing the strips in problem order.
+        // Within a bucket, pack_bucket keeps each problem's strips in one
+        // wavefront wherever strip counts fit (strip_pack.h).
         int waves = 0;
         for (int b = 2 * 64 + 1; b >= 0; --b) {
             const int bb = (b / 2) * 2 + (1 - b % 2);  // 2m before 2m + 1
             std::vector<Item> &v = strips[g][bb];
             if (v.empty()) continue;
-            const std::vector<Span> &sp = spans[g][bb];
-            std::vector<int> by_r[4];  // problems by remainder size 1..3
-            for (int i = 0; i < (int)sp.size(); ++i) {
-                const int full = sp[i].k / 4 * 4;
-                for (int j = 0; j < full; ++j) out.push_back(v[sp[i].first + j]);
-                if (sp[i].k > full) by_r[sp[i].k - full].push_back(i);
-            }
-            auto emit = [&](int i) {
-                for (int j = sp[i].k / 4 * 4; j < sp[i].k; ++j) out.push_back(v[sp[i].first + j]);
-            };
-            const std::vector<int> &r3 = by_r[3], &r2 = by_r[2], &r1 = by_r[1];
-            size_t i3 = 0, i2 = 0, i1 = 0;
-            for (; i3 < r3.size() && i1 < r1.size(); ++i3, ++i1) {
-                emit(r3[i3]);
-                emit(r1[i1]);
-            }
-            for (; i2 + 1 < r2.size(); i2 += 2) {
-                emit(r2[i2]);
-                emit(r2[i2 + 1]);
-            }
-            if (i2 < r2.size() && i1 + 1 < r1.size()) {
-                emit(r2[i2++]);
-                emit(r1[i1++]);
-                emit(r1[i1++]);
-            }
-            for (; i1 + 3 < r1.size(); i1 += 4)
-                for (int j = 0; j < 4; ++j) emit(r1[i1 + j]);
-            for (; i3 < r3.size(); ++i3) emit(r3[i3]);
-            for (; i2 < r2.size(); ++i2) emit(r2[i2]);
-            for (; i1 < r1.size(); ++i1) emit(r1[i1]);
+            pack_bucket(v, spans[g][bb], out);
             Item pad = v.back();
             pad.ncols = 0;
             while ((out.size() - (size_t)t->start[g]) % 4) out.push_back(pad);
