@@ -189,7 +189,8 @@ def measured_traffic(name, sources, ok=True):
 
 GEMM_SOURCES = ["paper_2608_25469_amd/csrc/gemm.hip"]
 SMALL_SOURCES = ["paper_2608_25469_amd/csrc/small_kernels.h", "paper_2608_25469_amd/csrc/dpp_fma.h",
-                 "paper_2608_25469_amd/csrc/strip.hip", "paper_2608_25469_amd/csrc/batched.cpp"]
+                 "paper_2608_25469_amd/csrc/strip.hip", "paper_2608_25469_amd/csrc/batched.cpp",
+                 "paper_2608_25469_amd/csrc/strip_pack.h"]
 
 
 def time_gpu(fn, steps, warmup, torch):
