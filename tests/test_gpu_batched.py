@@ -62,6 +62,34 @@ def test_batched_matches_oracle_and_single_calls():
         assert_parity(L, B, X, a, unit=u, tag=("batched", B.shape))
 
 
+def test_batched_every_m_with_three_or_four_blocks():
+    """m = 33 .. 64 (three or four 16-row blocks), real and complex: four
+    16-column problems of one m share a wavefront (each strip its own
+    problem), beside 40- and 64-column problems and a 5-column one.  Real
+    batches keep two finished blocks in LDS and read older ones back from B;
+    single calls keep them all, so equal bits check both walks."""
+    rng = np.random.default_rng(77)
+    probs = []
+    for m in range(33, 65):
+        for cx in (False, True):
+            for j, n in enumerate((16, 16, 16, 16, 40, 64, 5)):
+                L, B = W.problem(1000 * m + 10 * j + cx, m, n, cx)
+                unit = bool(rng.integers(0, 3) == 0)
+                alpha = complex(rng.uniform(-2, 2), rng.uniform(-1, 1)) if cx else float(rng.uniform(-2, 2))
+                probs.append((L, B, alpha, unit))
+    dev = to_dev(probs)
+    hs.trsm_batched(dev)
+    torch.cuda.synchronize()
+    dev1 = to_dev(probs)
+    for L, B, a, u in dev1:
+        hs.trsm(L, B, a, unit=u)
+    torch.cuda.synchronize()
+    for (L, B, a, u), (_, Bd, _, _), (_, Bs, _, _) in zip(probs, dev, dev1):
+        X = hs.from_colmajor(Bd)
+        assert X.tobytes() == hs.from_colmajor(Bs).tobytes(), ("batched differs from single call", B.shape)
+        assert_parity(L, B, X, a, unit=u, tag=("every m", B.shape, np.iscomplexobj(B), u))
+
+
 def test_batched_workload_subset():
     """2000 problems drawn like the 10 000-problem complex workload."""
     b = W.batched(count=2000)
