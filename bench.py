@@ -114,10 +114,10 @@ class RocBlas:
             f.argtypes = [vp, i32, i32, i32, i32, i32, i32, vp, vp, i32, vp, i32]
             f.restype = i32
 
-    def ztrsm_batched(self, m, n, alpha, A_ptrs, lda, B_ptrs, ldb, count):
-        """rocblas_ztrsm_batched (left, lower, no transpose, non-unit) on
-        device arrays of device pointers."""
-        f = self.lib.rocblas_ztrsm_batched
+    def trsm_batched(self, cx, m, n, alpha, A_ptrs, lda, B_ptrs, ldb, count):
+        """rocblas_ztrsm_batched or rocblas_dtrsm_batched (left, lower, no
+        transpose, non-unit) on device arrays of device pointers."""
+        f = self.lib.rocblas_ztrsm_batched if cx else self.lib.rocblas_dtrsm_batched
         vp, i32 = ctypes.c_void_p, ctypes.c_int32
         f.argtypes = [vp, i32, i32, i32, i32, i32, i32, vp, vp, i32, vp, i32, i32]
         f.restype = i32
@@ -125,7 +125,7 @@ class RocBlas:
         st = f(self.h, self.SIDE_LEFT, self.FILL_LOWER, self.OP_NONE, self.DIAG_NON_UNIT, m, n, a,
                ctypes.c_void_p(A_ptrs), lda, ctypes.c_void_p(B_ptrs), ldb, count)
         if st != 0:
-            raise RuntimeError(f"rocblas_ztrsm_batched: {st}")
+            raise RuntimeError(f"rocblas_{'z' if cx else 'd'}trsm_batched: {st}")
 
     SIDE = {"L": 141, "R": 142}
     UPLO = {"U": 121, "L": 122}
@@ -432,15 +432,18 @@ def run_batched(args, torch, hs, cfg):
     # The dominant kernel is the strip kernel.  Problems with m, n <= 16 ride
     # in its launch when the batch has other small problems (else they run in
     # the fused kernel's own launch, and are left out of its bytes).
+    cx = bool(cfg["complex_"])
+    es = 16 if cx else 8
     tiny = [(m_, n_) for m_, n_ in b.shapes if m_ <= 16 and n_ <= 16]
     tiny_launched = prof["tiny"]["launches"] > 0
-    byts_small = byts - (sum(W.algorithmic_bytes(m_, n_, True) for m_, n_ in tiny) if tiny_launched else 0)
+    byts_small = byts - (sum(W.algorithmic_bytes(m_, n_, cx) for m_, n_ in tiny) if tiny_launched else 0)
     sm = prof["small"]
     launches = max(1, sm["launches"] // args.steps)
     avg_launch_ms = sm["ms"] / max(1, sm["launches"])
     bytes_per_launch = byts_small / launches
     ach = bytes_per_launch / (avg_launch_ms * 1e-3) / 1e9
-    traffic = measured_traffic("strip_solve_batched10000_traffic", SMALL_SOURCES, count == cfg["count"])
+    traffic = measured_traffic("strip_solve_batched10000_traffic", SMALL_SOURCES,
+                               count == cfg["count"] and dict(cfg) == dict(W.BATCHED))
     roof = {"bound": "hbm", "kernel": "hsma_strip_solve (grouped: four 16-column strips per wavefront)",
             "achieved": round(ach, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic,
@@ -450,13 +453,13 @@ def run_batched(args, torch, hs, cfg):
             "fused_launch_ms_per_step": prof["tiny"]["ms"] / args.steps,
             "step_ms_events": ev_ms,
             "step_rate_gbs": round(byts / (ev_ms * 1e-3) / 1e9, 2),
-            "per_unit": "per problem: 16 (m(m+1)/2 + 2mn) bytes (lower triangle of L once, B read and "
+            "per_unit": f"per problem: {es} (m(m+1)/2 + 2mn) bytes (lower triangle of L once, B read and "
                         "written once); a launch serves one (dtype, diag) group, so bytes per "
                         "launch = bytes of the group's problems (one group here: every problem is "
-                        "complex with a non-unit diagonal, the ones with m, n <= 16 included as "
-                        "one-strip items)" if not tiny_launched else
-                        "per problem: 16 (m(m+1)/2 + 2mn) bytes; the problems with m, n <= 16 ran in "
-                        "the fused kernel's own launch and are not counted"}
+                        f"{'complex' if cx else 'real'} with a non-unit diagonal, the ones with "
+                        "m, n <= 16 included as one-strip items)" if not tiny_launched else
+                        f"per problem: {es} (m(m+1)/2 + 2mn) bytes; the problems with m, n <= 16 ran "
+                        "in the fused kernel's own launch and are not counted"}
 
     # One-shot API (host descriptors uploaded each call) for reference.
     oneshot_ms = time_gpu(lambda: hs.trsm_batched(probs), max(2, args.steps), 1, torch)
@@ -471,7 +474,8 @@ def run_batched(args, torch, hs, cfg):
                 for L, B in zip(vl, vb):
                     rb.trsm(L, B, b.alpha)
             rms = time_gpu(rb_loop, 2, 1, torch)
-            rocblas = {"kind": "rocblas_ztrsm called once per problem", "ms_per_step": round(rms, 3),
+            rocblas = {"kind": f"rocblas_{'z' if cx else 'd'}trsm called once per problem",
+                       "ms_per_step": round(rms, 3),
                        "solves_per_s": round(count / (rms * 1e-3), 1), "speedup_ours": round(rms / ms, 2)}
             # rocBLAS's batched call on each uniform (m, n) group of the batch
             groups = {}
@@ -486,9 +490,9 @@ def run_batched(args, torch, hs, cfg):
 
             def rb_groups():
                 for m_, n_, pa, pbp, cnt in ptrs:
-                    rb.ztrsm_batched(m_, n_, b.alpha, pa.data_ptr(), m_, pbp.data_ptr(), m_, cnt)
+                    rb.trsm_batched(cx, m_, n_, b.alpha, pa.data_ptr(), m_, pbp.data_ptr(), m_, cnt)
             gms = time_gpu(rb_groups, 3, 1, torch)
-            rocblas_batched = {"kind": "rocblas_ztrsm_batched once per uniform (m, n) group",
+            rocblas_batched = {"kind": f"rocblas_{'z' if cx else 'd'}trsm_batched once per uniform (m, n) group",
                                "groups": len(ptrs), "ms_per_step": round(gms, 3),
                                "solves_per_s": round(count / (gms * 1e-3), 1),
                                "speedup_ours": round(gms / ms, 2)}
@@ -521,7 +525,7 @@ def run_batched(args, torch, hs, cfg):
     gflops = fl / (ms * 1e-3) / 1e9
     return {
         "value": round(count / (ms * 1e-3), 1), "unit": "solves/s", "ms_per_step": round(ms, 4),
-        "dtype": "c128", "gflops": round(gflops, 2),
+        "dtype": "c128" if cx else "f64", "gflops": round(gflops, 2),
         "pct_fp64_peak": round(100 * gflops / (FP64_PEAK_TFLOPS * 1e3), 3),
         "solves_per_s": round(count / (ms * 1e-3), 1),
         "extra_config": {"count": count, "flops_per_step": fl, "bytes_per_step": byts,
@@ -1082,6 +1086,19 @@ def run_headline(args, torch, hs, names):
     except Exception as e:
         out["very_small_batched"] = {"error": repr(e)}
     try:
+        # The batched shapes as real problems (the strip kernel's real form).
+        rs = copy.copy(sub)
+        rs.workload, rs.steps, rs.warmup, rs.count = "batched_real", 20, 5, 0
+        r = run_batched(rs, torch, hs, dict(W.BATCHED_REAL))
+        out["batched_real"] = {"workload": names["batched_real"], "solves_per_s": r["value"],
+                               "ms_per_batch": r["ms_per_step"], "dtype": r["dtype"],
+                               "avg_launch_ms": r["roofline"]["avg_launch_ms"],
+                               "hbm_frac": r["roofline"]["frac"], "parity": r["parity"],
+                               "rocblas": r["rocblas"]}
+    except Exception as e:
+        out["batched_real"] = {"error": repr(e)}
+    torch.cuda.empty_cache()
+    try:
         out["cholesky"] = run_cholesky(sub, torch, hs)
     except Exception as e:
         out["cholesky"] = {"error": repr(e)}
@@ -1142,6 +1159,7 @@ def main():
              "large_real_fp32": "STRSM left-lower, m=n=16384, FP32, alpha=-1, seed 2 (the DTRSM draw rounded)",
              "large_complex_fp32": "CTRSM left-lower, m=n=8192, complex FP32, alpha=(-1,0), seed 2",
              "batched": "ZTRSM batched: 10000 solves, m,n ~ U{8..64}, alpha=(1,0.5), seed 1",
+             "batched_real": "DTRSM batched: 10000 solves, m,n ~ U{8..64}, alpha=0.5, seed 1",
              "single": "DTRSM left-lower, m=n=32, FP64, alpha=1, seed 0"}
     headline = None
     if args.workload == "default":

@@ -162,6 +162,8 @@ def mixed_problem(m: int = 8192, n: int = 4096, kappa: float = 1e3, seed: int = 
 # Batched small complex solves: 10 000 problems, m and n i.i.d. U{8..64},
 # alpha = (1, 0.5), seed 1.
 BATCHED = dict(seed=1, count=10000, lo=8, hi=64, complex_=True, alpha=complex(1.0, 0.5))
+# The same shapes as real problems (DTRSM), alpha = 0.5.
+BATCHED_REAL = dict(seed=1, count=10000, lo=8, hi=64, complex_=False, alpha=0.5)
 
 
 @dataclass
