@@ -2,19 +2,21 @@
 // wavefront.  The paper names kernel fusion for very small scales as future
 // work (Sec. 6).
 //
-// The small-solve kernel gives each problem a whole 64-lane wavefront (lane =
-// column) and stages L in 16-row blocks; a problem with n <= 16 then leaves
-// at least 48 lanes idle and m <= 16 uses a single, mostly empty block.  Here
-// each 16-lane quarter of the wavefront is one problem: its lower triangle
-// (<= 16 x 16) sits in the quarter's own LDS region, lane j of the quarter
-// holds column j in 16 registers, and the substitution chain
+// Each 16-lane quarter of the wavefront (one DPP row) is one problem.  Lane i
+// of the quarter holds row i of L in 16 registers and column i of B in 16
+// more; the substitution chain
 //     x_k <- x_k / l_kk,   x_i <- x_i - l_ik x_k  (i > k)
-// runs over the problem's own m.  The lanes of a quarter read the same l_ik
-// (an LDS broadcast); the four quarters' regions are offset so that their
-// four addresses fall in different banks.  Rows beyond m are zero in LDS and
-// in registers.  The per-problem arithmetic does not depend on which quarter
-// or launch a problem lands in, so a problem gives the same bits alone and
-// in a batch.
+// runs in the registers: at step k every lane scales its row k by lane k's
+// reciprocal of l_kk, and the coefficient l_ik reaches the lane through a
+// row broadcast of lane i's register that is the source operand of the
+// multiply-add (the diagonal walk of the strip kernel, on one 16-row block).
+// No LDS: occupancy is set by registers alone.  The walk stops after the
+// largest m among the wavefront's four problems.  Rows at or beyond a
+// problem's m hold a unit diagonal and zero coefficients, so every value
+// stays finite, and they only ever feed rows at or beyond m, which are never
+// stored.  The arithmetic of a problem does not depend on its quarter or
+// launch, and it is the strip kernel's, so a problem gives the same bits
+// alone, in a batch and in a strip.
 
 #include "small_kernels.h"
 
@@ -31,17 +33,10 @@ struct TinyItem {
 };
 
 constexpr int kMax = 16;
-// Quarter stride in elements: 16 x 17 plus padding that puts the four
-// quarters' copies of one element in different LDS banks.
-template <bool CX>
-constexpr int quarter_stride() { return CX ? 276 : 280; }
 
-// Element operations.  Every rounding is spelled out and in the same order
-// as in the strip kernel's walk (strip.hip, dpp_fma.h): the update of a
-// complex row is yr -= lr xr, yi -= lr xi, yr += li xi, yi -= li xr, each a
-// fused multiply-add; the diagonal is applied as a product with its
-// reciprocal; alpha scales only when it is not 1.  So a problem gives the
-// same bits here as there.
+// Element operations (loads, stores, alpha, the reciprocal of a diagonal
+// entry), rounded as in the strip kernel: alpha scales only when it is not
+// 1, and complex products are spelled out (cmul_rn, recip_rn).
 template <bool CX>
 struct D;
 template <>
@@ -51,14 +46,17 @@ struct D<false> {
     static __device__ __forceinline__ void st(HSMA_GLOBAL double *p, int64_t i, V v) { p[i] = v; }
     static __device__ __forceinline__ V zero() { return 0.0; }
     static __device__ __forceinline__ V one() { return 1.0; }
-    static __device__ __forceinline__ void fnms(V &acc, V l, V x) { acc = __fma_rn(-l, x, acc); }
-    static __device__ __forceinline__ V scale(V x, V r) { return __dmul_rn(x, r); }
     static __device__ __forceinline__ V alpha(V x, double ar, double) { return __dmul_rn(x, ar); }
     static __device__ __forceinline__ V recip(V d) {
         double r, i;
         smallk::recip_rn(false, d, 0.0, r, i);
         return r;
     }
+    static __device__ __forceinline__ void split(V v, double &r, double &i) {
+        r = v;
+        i = 0.0;
+    }
+    static __device__ __forceinline__ V join(double r, double) { return r; }
 };
 template <>
 struct D<true> {
@@ -71,19 +69,6 @@ struct D<true> {
     }
     static __device__ __forceinline__ V zero() { return V{0.0, 0.0}; }
     static __device__ __forceinline__ V one() { return V{1.0, 0.0}; }
-    static __device__ __forceinline__ void fnms(V &acc, V l, V x) {
-        double yr = acc.x, yi = acc.y;
-        yr = __fma_rn(-l.x, x.x, yr);
-        yi = __fma_rn(-l.x, x.y, yi);
-        yr = __fma_rn(l.y, x.y, yr);
-        yi = __fma_rn(-l.y, x.x, yi);
-        acc = V{yr, yi};
-    }
-    static __device__ __forceinline__ V scale(V x, V r) {
-        double a, b;
-        smallk::cmul_rn(x.x, x.y, r.x, r.y, a, b);
-        return V{a, b};
-    }
     static __device__ __forceinline__ V alpha(V x, double ar, double ai) {
         double a, b;
         smallk::cmul_rn(ar, ai, x.x, x.y, a, b);
@@ -94,33 +79,62 @@ struct D<true> {
         smallk::recip_rn(true, d.x, d.y, r, i);
         return V{r, i};
     }
+    static __device__ __forceinline__ void split(V v, double &r, double &i) {
+        r = v.x;
+        i = v.y;
+    }
+    static __device__ __forceinline__ V join(double r, double i) { return V{r, i}; }
 };
+
+// Step K of the walk: x_K is scaled by lane K's reciprocal of l_KK (one
+// product with the reciprocal, as in the strip kernel), then rows K+1..15
+// receive -l_iK x_K, with l_iK broadcast from lane i inside the multiply-add.
+// Steps from the wavefront's largest m on are skipped (mmax is uniform).
+template <bool CX, bool UNIT, int K>
+__device__ __forceinline__ void reg_walk(double (&xr)[kMax], double (&xi)[kMax], const double (&lr)[kMax],
+                                         const double (&li)[kMax], double rr, double ri, int mmax) {
+    if constexpr (K < kMax) {
+        if (K >= mmax) return;
+        if (!UNIT) {
+            const double dr = smallk::bcast16<K>(rr);
+            if (CX) {
+                const double di = smallk::bcast16<K>(ri);
+                smallk::cmul_rn(xr[K], xi[K], dr, di, xr[K], xi[K]);
+            } else {
+                xr[K] = __dmul_rn(xr[K], dr);
+            }
+        }
+        if constexpr (K + 1 < kMax) smallk::fnma_rows<CX, K + 1>(xr, xi, lr[K], li[K], xr[K], xi[K]);
+        reg_walk<CX, UNIT, K + 1>(xr, xi, lr, li, rr, ri, mmax);
+    }
+}
 
 // Workgroup b solves items 4b .. 4b + 3 (those below count); with items ==
 // nullptr it solves `one` alone (a single call, no descriptor upload).
+// Every lane stays active through the walk: lanes beyond a problem's n still
+// hold rows of L that the others receive by broadcast.
 template <bool CX, bool UNIT>
 __global__ __launch_bounds__(64) void hsma_tiny(TinyItem one, const TinyItem *__restrict__ items,
                                                 int count) {
     typedef D<CX> O;
     typedef typename O::V V;
-    constexpr int QS = quarter_stride<CX>();
-    __shared__ V Ls[4 * QS];
     const int q = threadIdx.x >> 4, lane = threadIdx.x & 15;
     const int idx = blockIdx.x * 4 + q;
     const bool active = items ? idx < count : q == 0;
     TinyItem it = one;
     if (items && active) it = items[idx];
-    V *L = Ls + q * QS;
-    __shared__ V Rs[4 * kMax];  // reciprocals of each quarter's diagonal
-    V *Rq = Rs + q * kMax;
+    if (!active) it.m = it.ncols = 0;
     // alpha == 0: B <- 0, and neither A nor B is read (A may be null).
     const bool azero = it.ar == 0.0 && (!CX || it.ai == 0.0);
-    const int m = (active && !azero) ? it.m : 0;
+    const int m = azero ? 0 : it.m;
+    // the largest m of the wavefront's four problems
+    int mmax = __builtin_amdgcn_readlane(m, 0);
+    mmax = max(mmax, __builtin_amdgcn_readlane(m, 16));
+    mmax = max(mmax, __builtin_amdgcn_readlane(m, 32));
+    mmax = max(mmax, __builtin_amdgcn_readlane(m, 48));
     const HSMA_GLOBAL double *A = (const HSMA_GLOBAL double *)it.A;
-    // Stage the quarter's lower triangle (16 x 16, ld 17; zero elsewhere):
-    // lane i of the quarter takes row i of every column, so each column is
-    // one contiguous read, and the unrolled loop issues all 16 loads before
-    // the first LDS store waits for one.
+    // Row i of L: this lane's coefficients (zero elsewhere, 1 on the diagonal
+    // of rows >= m); all 16 loads are issued before the first use.
     const int i = lane;
     V lv[kMax];
 #pragma unroll
@@ -128,41 +142,38 @@ __global__ __launch_bounds__(64) void hsma_tiny(TinyItem one, const TinyItem *__
         const bool rd = i < m && k < m && (UNIT ? k < i : k <= i);
         lv[k] = rd ? O::ld(A, i + (int64_t)k * it.lda) : (i == k ? O::one() : O::zero());
     }
+    // Column `lane` of B (zero beyond m and beyond n).
+    const bool own = lane < it.ncols;
+    HSMA_GLOBAL double *col = (HSMA_GLOBAL double *)it.B + (CX ? 2 : 1) * (int64_t)lane * it.ldb;
+    V x[kMax];
 #pragma unroll
-    for (int k = 0; k < kMax; ++k) L[i + k * (kMax + 1)] = lv[k];
+    for (int r = 0; r < kMax; ++r) x[r] = (own && r < m) ? O::ld(col, r) : O::zero();
+    // Reciprocal of this lane's diagonal entry (row i).
+    V rcp = O::one();
     if (!UNIT) {
         V d = O::one();
 #pragma unroll
         for (int k = 0; k < kMax; ++k)
             if (k == i) d = lv[k];
-        Rq[i] = O::recip(d);
+        rcp = O::recip(d);
     }
-    __syncthreads();
-    if (!active || lane >= it.ncols) return;
-    HSMA_GLOBAL double *col = (HSMA_GLOBAL double *)it.B + (CX ? 2 : 1) * (int64_t)lane * it.ldb;
-    if (azero) {
-        for (int r = 0; r < it.m; ++r) O::st(col, r, O::zero());
-        return;
-    }
-    V x[kMax];
-#pragma unroll
-    for (int r = 0; r < kMax; ++r) x[r] = r < m ? O::ld(col, r) : O::zero();  // all loads in flight
     if (it.ar != 1.0 || it.ai != 0.0) {
 #pragma unroll
         for (int r = 0; r < kMax; ++r) x[r] = O::alpha(x[r], it.ar, it.ai);
     }
+    double xr[kMax], xi[kMax], lr[kMax], li[kMax];
 #pragma unroll
-    for (int k = 0; k < kMax; ++k) {
-        if (k < m) {
-            if (!UNIT) x[k] = O::scale(x[k], Rq[k]);
-            const V xk = x[k];
-#pragma unroll
-            for (int r = k + 1; r < kMax; ++r) O::fnms(x[r], L[r + k * (kMax + 1)], xk);
-        }
+    for (int r = 0; r < kMax; ++r) {
+        O::split(x[r], xr[r], xi[r]);
+        O::split(lv[r], lr[r], li[r]);
     }
+    double rr, ri;
+    O::split(rcp, rr, ri);
+    reg_walk<CX, UNIT, 0>(xr, xi, lr, li, rr, ri, mmax);
+    if (!own) return;
 #pragma unroll
     for (int r = 0; r < kMax; ++r)
-        if (r < m) O::st(col, r, x[r]);
+        if (r < it.m) O::st(col, r, azero ? O::zero() : O::join(xr[r], xi[r]));
 }
 
 template <bool CX>
