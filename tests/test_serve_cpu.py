@@ -249,9 +249,13 @@ def test_blocked_classes_split_by_size_and_data_type():
     size class: four class launches on four different streams, each modelled
     as fixed + its own flops / rate, so each request finishes at its own
     class's modelled time (a launch shared by the real and the complex
-    request of a class would finish both at the summed time)."""
+    request of a class would finish both at the summed time).  The real
+    requests have four times the columns, so the two requests of a class
+    model the same time and a shared launch would double it: the bound
+    (40 % over the model) separates the two with room for a late wake-up of
+    the retiring thread on a busy host."""
     rate, fixed = 0.05, 1_000.0
-    shapes = [(200, 10, False), (200, 10, True), (600, 10, False), (600, 10, True)]
+    shapes = [(200, 40, False), (200, 10, True), (600, 40, False), (600, 10, True)]
     with sim_queue(rate_flops_per_ns=rate, fixed_ns=fixed, n_streams=8) as q:
         tk = q.submit([dev_req(m, n, cx=cx) for m, n, cx in shapes])
         infos = wait_all(q, tk)
@@ -260,7 +264,7 @@ def test_blocked_classes_split_by_size_and_data_type():
     for (m, n, cx), i in zip(shapes, infos):
         model = fixed + m * m * n * (4.0 if cx else 1.0) / rate
         took = i["t_done_ns"] - i["t_admit_ns"]
-        assert model * 0.999 <= took <= model + 5 * MS, (m, cx, took, model)
+        assert model * 0.999 <= took <= 1.4 * model, (m, cx, took, model)
 
 
 def exact_pct(v, q):
