@@ -42,8 +42,9 @@ struct Z<false> {
     static __device__ __forceinline__ double re(V v) { return v; }
     static __device__ __forceinline__ V scale(V v, double s) { return v * s; }
     // a - b conj(c)
-    static __device__ __forceinline__ V fnms_conj(V a, V b, V c) { return a - b * c; }
+    static __device__ __forceinline__ V fnms_conj(V a, V b, V c) { return __fma_rn(-b, c, a); }
     static __device__ __forceinline__ V real(double d) { return d; }
+    static __device__ __forceinline__ V bcast(V v, int l);
 };
 template <>
 struct Z<true> {
@@ -57,25 +58,43 @@ struct Z<true> {
     static __device__ __forceinline__ double re(V v) { return v.x; }
     static __device__ __forceinline__ V scale(V v, double s) { return V{v.x * s, v.y * s}; }
     static __device__ __forceinline__ V fnms_conj(V a, V b, V c) {
-        // b conj(c) = (br cr + bi ci, bi cr - br ci)
-        return V{a.x - (b.x * c.x + b.y * c.y), a.y - (b.y * c.x - b.x * c.y)};
+        // b conj(c) = (br cr + bi ci, bi cr - br ci), as four fused steps
+        const double x = __fma_rn(-b.y, c.y, __fma_rn(-b.x, c.x, a.x));
+        const double y = __fma_rn(b.x, c.y, __fma_rn(-b.y, c.x, a.y));
+        return V{x, y};
     }
     static __device__ __forceinline__ V real(double d) { return V{d, 0.0}; }
+    static __device__ __forceinline__ V bcast(V v, int l);
 };
 
+// Lane l's value of v, to every lane (a wavefront-uniform scalar).
+__device__ __forceinline__ double from_lane(double v, int l) {
+    const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, l);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), l);
+    return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
+__device__ __forceinline__ double Z<false>::bcast(double v, int l) { return from_lane(v, l); }
+__device__ __forceinline__ dbl2u Z<true>::bcast(dbl2u v, int l) {
+    return dbl2u{from_lane(v.x, l), from_lane(v.y, l)};
+}
+
 // One n x n diagonal block (n <= 64), right-looking, in registers: lane i
-// holds row i of the lower triangle (a_ic, c <= i).  At step j lane j
-// publishes sqrt(a_jj); every lane below scales its a_ij by the reciprocal
-// and publishes it, then updates its own row, a_ic -= l_ij conj(l_cj) for
-// j < c <= i, reading column j from LDS (a broadcast: all lanes read the same
-// l_cj).  Rows are loaded and stored column by column, consecutive lanes on
+// holds row i of the lower triangle (a_ic, c <= i).  At step j every lane
+// takes lane j's a_jj, forms d = sqrt(a_jj) and 1/d; lanes below j scale
+// their a_ij by 1/d, lane j keeps d; then every lane updates its row,
+// a_ic -= l_ij conj(l_cj) for c > j, with l_cj read from lane c's register
+// as a scalar operand (no LDS, no barrier).  The update runs on every column
+// c > j of every lane, without a per-element test: entries right of a
+// lane's diagonal (c > i) and rows at or beyond n take values that are
+// never stored and never read as l_cj (only lanes c > j are read at step j).
+// Rows are loaded and stored column by column, consecutive lanes on
 // consecutive rows.
 template <bool CX>
 __global__ __launch_bounds__(64) void hsma_potrf_base(double *__restrict__ A, int64_t lda, int n) {
     typedef Z<CX> O;
     typedef typename O::V V;
-    __shared__ V colj[kBase];
-    __shared__ double piv;
     const int i = threadIdx.x;
     const bool row_ok = i < n;
     V r[kBase];
@@ -85,22 +104,13 @@ __global__ __launch_bounds__(64) void hsma_potrf_base(double *__restrict__ A, in
 #pragma unroll
     for (int j = 0; j < kBase; ++j) {
         if (j < n) {
-            if (i == j) piv = sqrt(O::re(r[j]));
-            __syncthreads();
-            const double d = piv;
-            if (i == j) r[j] = O::real(d);
-            if (i > j && row_ok) {
-                r[j] = O::scale(r[j], 1.0 / d);
-                colj[i] = r[j];
-            }
-            __syncthreads();
-            if (i > j && row_ok) {
-                const V lij = r[j];
+            const double d = sqrt(from_lane(O::re(r[j]), j));
+            const double inv = 1.0 / d;
+            const V rj = r[j];
+            r[j] = i > j ? O::scale(rj, inv) : (i == j ? O::real(d) : rj);
+            const V lij = r[j];
 #pragma unroll
-                for (int c = j + 1; c < kBase; ++c)
-                    if (c <= i) r[c] = O::fnms_conj(r[c], lij, colj[c]);
-            }
-            __syncthreads();  // column j read before the next step writes
+            for (int c = j + 1; c < kBase; ++c) r[c] = O::fnms_conj(r[c], lij, O::bcast(r[j], c));
         }
     }
 #pragma unroll
