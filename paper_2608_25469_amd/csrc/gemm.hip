@@ -34,6 +34,8 @@
 // tiles, walked in groups of 8 tile-rows so neighbouring workgroups share A
 // and B panels in that XCD's L2.
 
+#include <algorithm>
+
 #include "internal.h"
 
 namespace hsma {
@@ -389,7 +391,41 @@ hsma_status launch_role(GemmParams p, int count, hipStream_t s) {
         return HSMA_NOT_SUPPORTED;
     }
     if (p.M <= 64 && p.N <= 64) return launch_t<CX, 64, 64, 2, 2, ROLE>(p, count, s);
-    if (ROLE == (int)GemmRole::Update || ROLE == (int)GemmRole::Herk) {
+    if (ROLE == (int)GemmRole::Herk) {
+        // Lower-triangular C: only tiles on or below the diagonal run, and
+        // each runs the whole K, so the launch takes about ceil(tiles /
+        // resident slots) rounds of one tile's time.  Pick the shape with the
+        // fewest rounds times tile area, weighted by the shape's relative
+        // throughput (narrower tiles reuse less of what they stage).
+        DeviceInfo dev;
+        const int64_t cus = (device_info(&dev) == HSMA_SUCCESS && dev.num_cus > 0) ? dev.num_cus : 256;
+        struct Shape {
+            int bm, bn;
+            double eff;
+        };
+        const Shape shapes[3] = {{128, 128, 1.0}, {128, 64, 0.85}, {64, 64, 0.7}};
+        int best = 0;
+        double best_cost = 0.0;
+        for (int k = 0; k < 3; ++k) {
+            const int bm = shapes[k].bm, bn = shapes[k].bn;
+            const int64_t tm_n = (p.M + bm - 1) / bm, tn_n = (p.N + bn - 1) / bn;
+            int64_t tiles = 0;
+            for (int64_t tm = 0; tm < tm_n; ++tm) {
+                const int64_t last = CX ? (tm * bm + bm - 1) / 2 : tm * bm + bm - 1;
+                tiles += std::min<int64_t>(tn_n, last / bn + 1);
+            }
+            const int64_t slots = (int64_t)occ_for(bm, bn) * cus;
+            const double cost = (double)((tiles * count + slots - 1) / slots) * bm * bn / shapes[k].eff;
+            if (k == 0 || cost < best_cost) {
+                best = k;
+                best_cost = cost;
+            }
+        }
+        if (best == 0) return launch_t<CX, 128, 128, 2, 2, ROLE>(p, count, s);
+        if (best == 1) return launch_t<CX, 128, 64, 2, 2, ROLE>(p, count, s);
+        return launch_t<CX, 64, 64, 2, 2, ROLE>(p, count, s);
+    }
+    if (ROLE == (int)GemmRole::Update) {
         // The trailing updates of the deepest recursion levels are thin
         // (M = K = one or two block sizes): below HSMA_UPD_MIN_WG_PER_CU
         // workgroups per CU, narrower tiles keep every CU busy.
