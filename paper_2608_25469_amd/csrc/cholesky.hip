@@ -44,7 +44,6 @@ struct Z<false> {
     // a - b conj(c)
     static __device__ __forceinline__ V fnms_conj(V a, V b, V c) { return __fma_rn(-b, c, a); }
     static __device__ __forceinline__ V real(double d) { return d; }
-    static __device__ __forceinline__ V bcast(V v, int l);
 };
 template <>
 struct Z<true> {
@@ -64,7 +63,6 @@ struct Z<true> {
         return V{x, y};
     }
     static __device__ __forceinline__ V real(double d) { return V{d, 0.0}; }
-    static __device__ __forceinline__ V bcast(V v, int l);
 };
 
 // Lane l's value of v, to every lane (a wavefront-uniform scalar).
@@ -75,53 +73,66 @@ __device__ __forceinline__ double from_lane(double v, int l) {
     return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
 }
 
-__device__ __forceinline__ double Z<false>::bcast(double v, int l) { return from_lane(v, l); }
-__device__ __forceinline__ dbl2u Z<true>::bcast(dbl2u v, int l) {
-    return dbl2u{from_lane(v.x, l), from_lane(v.y, l)};
-}
-
-// One n x n diagonal block (n <= 64), right-looking, in registers: lane i
-// holds row i of the lower triangle (a_ic, c <= i).  At step j every lane
-// takes lane j's a_jj, forms d = sqrt(a_jj) and 1/d; lanes below j scale
-// their a_ij by 1/d, lane j keeps d; then every lane updates its row,
-// a_ic -= l_ij conj(l_cj) for c > j, with l_cj read from lane c's register
-// as a scalar operand (no LDS, no barrier).  The update runs on every column
-// c > j of every lane, without a per-element test: entries right of a
-// lane's diagonal (c > i) and rows at or beyond n take values that are
-// never stored and never read as l_cj (only lanes c > j are read at step j).
-// Rows are loaded and stored column by column, consecutive lanes on
-// consecutive rows.
+// One n x n diagonal block (n <= 64), right-looking, on four wavefronts:
+// lane i of every wavefront holds row i, and wavefront w the columns c with
+// c % 4 == w (16 of them, c = 4u + w in slot u).  At step j the wavefront
+// that owns column j takes lane j's a_jj (a lane read), forms d = sqrt(a_jj)
+// and 1/d, scales its a_ij by 1/d in the lanes below j (lane j keeps d), and
+// publishes the column in LDS; after one barrier every wavefront updates its
+// own columns c > j, a_ic -= l_ij conj(l_cj), with l_ij and l_cj read from
+// that LDS column (a broadcast for l_cj).  The column buffer alternates
+// between two copies, so a step's writes never meet the previous step's
+// reads and one barrier per step suffices.  Entries right of a lane's
+// diagonal and rows at or beyond n take values that are never stored and
+// never read as l_cj (only rows c > j are read at step j).  Rows are loaded
+// and stored column by column, consecutive lanes on consecutive rows.
 template <bool CX>
-__global__ __launch_bounds__(64) void hsma_potrf_base(double *__restrict__ A, int64_t lda, int n) {
+__global__ __launch_bounds__(256) void hsma_potrf_base(double *__restrict__ A, int64_t lda, int n) {
     typedef Z<CX> O;
     typedef typename O::V V;
-    const int i = threadIdx.x;
+    constexpr int NW = 4, NU = kBase / NW;
+    __shared__ V col[2][kBase];
+    const int i = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const bool row_ok = i < n;
-    V r[kBase];
+    V r[NU];
 #pragma unroll
-    for (int c = 0; c < kBase; ++c)
-        r[c] = (row_ok && c <= i && c < n) ? O::ld(A, i + (int64_t)c * lda) : O::real(0.0);
+    for (int u = 0; u < NU; ++u) {
+        const int c = NW * u + w;
+        r[u] = (row_ok && c <= i && c < n) ? O::ld(A, i + (int64_t)c * lda) : O::real(0.0);
+    }
 #pragma unroll
     for (int j = 0; j < kBase; ++j) {
         if (j < n) {
-            const double d = sqrt(from_lane(O::re(r[j]), j));
-            const double inv = 1.0 / d;
-            const V rj = r[j];
-            r[j] = i > j ? O::scale(rj, inv) : (i == j ? O::real(d) : rj);
-            const V lij = r[j];
+            V *cj = col[j & 1];
+            if (w == (j % NW)) {
+                const int uj = j / NW;
+                const double d = sqrt(from_lane(O::re(r[uj]), j));
+                const double inv = 1.0 / d;
+                const V rj = r[uj];
+                r[uj] = i > j ? O::scale(rj, inv) : (i == j ? O::real(d) : rj);
+                cj[i] = r[uj];
+            }
+            __syncthreads();
+            const V lij = cj[i];
 #pragma unroll
-            for (int c = j + 1; c < kBase; ++c) r[c] = O::fnms_conj(r[c], lij, O::bcast(r[j], c));
+            for (int u = 0; u < NU; ++u) {
+                const int c = NW * u + w;
+                if (c > j) r[u] = O::fnms_conj(r[u], lij, cj[c]);
+            }
         }
     }
 #pragma unroll
-    for (int c = 0; c < kBase; ++c)
-        if (row_ok && c <= i && c < n) O::st(A, i + (int64_t)c * lda, r[c]);
+    for (int u = 0; u < NU; ++u) {
+        const int c = NW * u + w;
+        if (row_ok && c <= i && c < n) O::st(A, i + (int64_t)c * lda, r[u]);
+    }
 }
 
 hsma_status potrf_base(bool cx, int n, double *A, int64_t lda, hipStream_t s) {
     ProfScope prof(HSMA_PHASE_FACTOR, (cx ? 4.0 : 1.0) * n * (double)n * n / 3.0, s);
-    if (cx) hipLaunchKernelGGL(hsma_potrf_base<true>, dim3(1), dim3(64), 0, s, A, lda, n);
-    else hipLaunchKernelGGL(hsma_potrf_base<false>, dim3(1), dim3(64), 0, s, A, lda, n);
+    if (cx) hipLaunchKernelGGL(hsma_potrf_base<true>, dim3(1), dim3(256), 0, s, A, lda, n);
+    else hipLaunchKernelGGL(hsma_potrf_base<false>, dim3(1), dim3(256), 0, s, A, lda, n);
     HSMA_HIP(hipGetLastError());
     return HSMA_SUCCESS;
 }
