@@ -289,3 +289,29 @@ def test_graph_one_capture_per_shape_new_pointers_and_alpha():
         assert after["updates"] - before["updates"] >= 10, (before, after)
         assert after["replays"] - before["replays"] == 30
     hs.graph_cache_clear()
+
+
+def test_plain_solve_on_side_streams():
+    """A plain solve (the options-free entry point) runs on torch's current
+    stream, or on the stream passed as an object or a raw handle: the
+    binding's stream lookup returns the side stream's handle inside its
+    context, and every result equals the default stream's bit for bit."""
+    for m, n, cx in ((32, 32, False), (40, 70, True), (300, 64, False)):
+        L, B = W.problem(4242 + m, m, n, cx)
+        Ld = hs.to_colmajor(L)
+        ref = hs.to_colmajor(B)
+        hs.trsm(Ld, ref, 1.0)
+        torch.cuda.synchronize()
+        want = hs.from_colmajor(ref).tobytes()
+        side = torch.cuda.Stream()
+        outs = [hs.to_colmajor(B) for _ in range(3)]
+        torch.cuda.synchronize()
+        with torch.cuda.stream(side):
+            assert hs._stream_handle(None) == side.cuda_stream
+            hs.trsm(Ld, outs[0], 1.0)
+        hs.trsm(Ld, outs[1], 1.0, stream=side)
+        hs.trsm(Ld, outs[2], 1.0, stream=side.cuda_stream)
+        side.synchronize()
+        assert hs._stream_handle(None) == torch.cuda.current_stream().cuda_stream
+        for k, o in enumerate(outs):
+            assert hs.from_colmajor(o).tobytes() == want, (m, n, cx, k)
