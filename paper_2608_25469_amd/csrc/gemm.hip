@@ -37,6 +37,7 @@
 #include <algorithm>
 
 #include "internal.h"
+#include "tile_choice.h"
 
 namespace hsma {
 namespace {
@@ -58,12 +59,9 @@ constexpr int BK = 16;
 
 // Workgroups per CU that the tile's LDS ring allows (160 KB per CU, at most
 // 3); the launch bound then caps registers so that many stay resident.
-__host__ __device__ constexpr int lds_bytes(int bm, int bn) {
-    return 2 * (BK * (bm + 4) + bn * (BK + 1)) * 8;
-}
-__host__ __device__ constexpr int occ_for(int bm, int bn) {
-    return (160 * 1024 / lds_bytes(bm, bn)) >= 3 ? 3 : ((160 * 1024 / lds_bytes(bm, bn)) >= 2 ? 2 : 1);
-}
+static_assert(BK == kTileBK, "one slice depth for the kernels and the shape choice");
+__host__ __device__ constexpr int lds_bytes(int bm, int bn) { return tile_lds_bytes(bm, bn); }
+__host__ __device__ constexpr int occ_for(int bm, int bn) { return tile_occupancy(bm, bn); }
 
 #ifndef HSMA_UPD_MIN_WG_PER_CU
 #define HSMA_UPD_MIN_WG_PER_CU 4
@@ -392,35 +390,11 @@ hsma_status launch_role(GemmParams p, int count, hipStream_t s) {
     }
     if (p.M <= 64 && p.N <= 64) return launch_t<CX, 64, 64, 2, 2, ROLE>(p, count, s);
     if (ROLE == (int)GemmRole::Herk) {
-        // Lower-triangular C: only tiles on or below the diagonal run, and
-        // each runs the whole K, so the launch takes about ceil(tiles /
-        // resident slots) rounds of one tile's time.  Pick the shape with the
-        // fewest rounds times tile area, weighted by the shape's relative
-        // throughput (narrower tiles reuse less of what they stage).
+        // Lower-triangular C: the shape with the fewest rounds of non-empty
+        // tiles (tile_choice.h).
         DeviceInfo dev;
         const int64_t cus = (device_info(&dev) == HSMA_SUCCESS && dev.num_cus > 0) ? dev.num_cus : 256;
-        struct Shape {
-            int bm, bn;
-            double eff;
-        };
-        const Shape shapes[3] = {{128, 128, 1.0}, {128, 64, 0.85}, {64, 64, 0.7}};
-        int best = 0;
-        double best_cost = 0.0;
-        for (int k = 0; k < 3; ++k) {
-            const int bm = shapes[k].bm, bn = shapes[k].bn;
-            const int64_t tm_n = (p.M + bm - 1) / bm, tn_n = (p.N + bn - 1) / bn;
-            int64_t tiles = 0;
-            for (int64_t tm = 0; tm < tm_n; ++tm) {
-                const int64_t last = CX ? (tm * bm + bm - 1) / 2 : tm * bm + bm - 1;
-                tiles += std::min<int64_t>(tn_n, last / bn + 1);
-            }
-            const int64_t slots = (int64_t)occ_for(bm, bn) * cus;
-            const double cost = (double)((tiles * count + slots - 1) / slots) * bm * bn / shapes[k].eff;
-            if (k == 0 || cost < best_cost) {
-                best = k;
-                best_cost = cost;
-            }
-        }
+        const int best = lower_tile_shape(p.M, p.N, CX, count, cus);
         if (best == 0) return launch_t<CX, 128, 128, 2, 2, ROLE>(p, count, s);
         if (best == 1) return launch_t<CX, 128, 64, 2, 2, ROLE>(p, count, s);
         return launch_t<CX, 64, 64, 2, 2, ROLE>(p, count, s);
