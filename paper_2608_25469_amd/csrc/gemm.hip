@@ -432,6 +432,10 @@ typedef float flt4 __attribute__((ext_vector_type(4)));
 
 template <int BM, int BN, int WM, int WN, int KCHUNK>
 __global__ __launch_bounds__(256, 2) void hsma_gemm_f32mfma(const GemmParams p) {
+    // 32-deep K slices here (the FP64 kernel takes 16): a slice of FP32
+    // products is half as long on the matrix cores, and a deeper one halves
+    // the barriers and stores per product (51 KB of LDS per workgroup).
+    constexpr int BK = 32;
     constexpr int TM = BM / WM, TN = BN / WN;
     constexpr int FM = TM / 16, FN = TN / 16;
     constexpr int LDA_S = BM + 4;
