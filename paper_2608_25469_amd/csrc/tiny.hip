@@ -10,8 +10,10 @@
 // reciprocal of l_kk, and the coefficient l_ik reaches the lane through a
 // row broadcast of lane i's register that is the source operand of the
 // multiply-add (the diagonal walk of the strip kernel, on one 16-row block).
-// No LDS: occupancy is set by registers alone.  The walk stops after the
-// largest m among the wavefront's four problems.  Rows at or beyond a
+// B moves through a small LDS stage (one 16 x 16 block per quarter) so that
+// global loads and stores walk down columns, 16 lanes on one segment; L's
+// rows are read straight into registers.  The walk stops after the largest m
+// among the wavefront's four problems.  Rows at or beyond a
 // problem's m hold a unit diagonal and zero coefficients, so every value
 // stays finite, and they only ever feed rows at or beyond m, which are never
 // stored.  The arithmetic of a problem does not depend on its quarter or
@@ -142,12 +144,24 @@ __global__ __launch_bounds__(64) void hsma_tiny(TinyItem one, const TinyItem *__
         const bool rd = i < m && k < m && (UNIT ? k < i : k <= i);
         lv[k] = rd ? O::ld(A, i + (int64_t)k * it.lda) : (i == k ? O::one() : O::zero());
     }
-    // Column `lane` of B (zero beyond m and beyond n).
-    const bool own = lane < it.ncols;
-    HSMA_GLOBAL double *col = (HSMA_GLOBAL double *)it.B + (CX ? 2 : 1) * (int64_t)lane * it.ldb;
+    // B passes through an LDS stage in whole column segments: lane r of the
+    // quarter reads row r of every column (the quarter's 16 lanes on one
+    // segment), and lane c then takes column c (zero beyond m and n).
+    __shared__ V Bs[4 * kMax * (kMax + 1)];
+    V *Bq = Bs + q * kMax * (kMax + 1);
+    HSMA_GLOBAL double *Bb = (HSMA_GLOBAL double *)it.B;
+    {
+        V t[kMax];
+#pragma unroll
+        for (int c = 0; c < kMax; ++c)
+            t[c] = (lane < m && c < it.ncols) ? O::ld(Bb, lane + (int64_t)c * it.ldb) : O::zero();
+#pragma unroll
+        for (int c = 0; c < kMax; ++c) Bq[c * (kMax + 1) + lane] = t[c];
+    }
+    __builtin_amdgcn_wave_barrier();
     V x[kMax];
 #pragma unroll
-    for (int r = 0; r < kMax; ++r) x[r] = (own && r < m) ? O::ld(col, r) : O::zero();
+    for (int r = 0; r < kMax; ++r) x[r] = Bq[lane * (kMax + 1) + r];
     // Reciprocal of this lane's diagonal entry (row i).
     V rcp = O::one();
     if (!UNIT) {
@@ -170,10 +184,14 @@ __global__ __launch_bounds__(64) void hsma_tiny(TinyItem one, const TinyItem *__
     double rr, ri;
     O::split(rcp, rr, ri);
     reg_walk<CX, UNIT, 0>(xr, xi, lr, li, rr, ri, mmax);
-    if (!own) return;
+    // back through the stage: lane c writes column c, lane r stores row r
+    __builtin_amdgcn_wave_barrier();
 #pragma unroll
-    for (int r = 0; r < kMax; ++r)
-        if (r < it.m) O::st(col, r, azero ? O::zero() : O::join(xr[r], xi[r]));
+    for (int r = 0; r < kMax; ++r) Bq[lane * (kMax + 1) + r] = azero ? O::zero() : O::join(xr[r], xi[r]);
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int c = 0; c < kMax; ++c)
+        if (lane < it.m && c < it.ncols) O::st(Bb, lane + (int64_t)c * it.ldb, Bq[c * (kMax + 1) + lane]);
 }
 
 template <bool CX>
