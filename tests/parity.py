@@ -19,6 +19,16 @@ U = 2.0 ** -53
 REL_BAR = 1e-12
 
 
+def padding_rows(t):
+    """Rows m .. ld - 1 of every column of the column-major m x n tensor t
+    (a view of its storage, shape (n, ld - m)).  A slice of t itself cannot
+    reach them: t covers rows 0 .. m - 1 only."""
+    m, n = t.shape
+    ld = t.stride(1)
+    full = t.as_strided((n, ld), (ld, 1), t.storage_offset())
+    return full[:, m:]
+
+
 def column_rel_errors(X, ref):
     """Per-column relative 2-norm errors (a zero reference column counts its
     absolute error)."""

@@ -5,7 +5,7 @@ import pytest
 
 import oracle
 import workloads as W
-from parity import assert_parity
+from parity import assert_parity, padding_rows
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -204,6 +204,47 @@ def test_more_items_than_one_grid_row():
     x1 = (b1 - l10 * x0) * (1.0 / l11)
     assert np.array_equal(X[:, 0], x0)
     assert np.array_equal(X[:, 1], x1)
+
+
+def test_fused_very_small_padded_and_alpha_zero():
+    """The fused kernel on problems whose B and L carry padding rows (ldb =
+    m + 5, lda = m + 3): the padding of B keeps its sentinel, problems with
+    alpha = 0 come back as exact zeros, and the rest match the oracle and
+    their single calls bit for bit."""
+    rng = np.random.default_rng(78)
+    probs, dev = [], []
+    for i in range(600):
+        m, n = int(rng.integers(1, 17)), int(rng.integers(1, 17))
+        cx, unit = bool(i % 2), bool(i % 3 == 0)
+        L, B = W.problem(60000 + i, m, n, cx)
+        if i % 7 == 0:
+            alpha = 0.0
+        else:
+            alpha = complex(rng.uniform(-2, 2), rng.uniform(-1, 1)) if cx else float(rng.uniform(-2, 2))
+        probs.append((L, B, alpha, unit))
+    def padded():
+        out = []
+        for L, B, a, u in probs:
+            Bd = hs.to_colmajor(B, ld=B.shape[0] + 5)
+            padding_rows(Bd).fill_(W.PAD_SENTINEL)
+            out.append((hs.to_colmajor(L, ld=L.shape[0] + 3), Bd, a, u))
+        return out
+    dev = padded()
+    hs.trsm_batched(dev)
+    torch.cuda.synchronize()
+    dev1 = padded()
+    for L, B, a, u in dev1:
+        hs.trsm(L, B, a, unit=u)
+    torch.cuda.synchronize()
+    for k, ((L, B, a, u), (_, Bd, _, _), (_, Bs, _, _)) in enumerate(zip(probs, dev, dev1)):
+        m = B.shape[0]
+        assert np.all(padding_rows(Bd).cpu().numpy() == W.PAD_SENTINEL), ("padding", k)
+        X = hs.from_colmajor(Bd)
+        assert X.tobytes() == hs.from_colmajor(Bs).tobytes(), ("batched differs from single", k)
+        if a == 0:
+            assert not np.any(X), ("alpha zero", k)
+        else:
+            assert_parity(L, B, X, a, unit=u, tag=("fused padded", k, B.shape))
 
 
 def test_fused_very_small_batch():

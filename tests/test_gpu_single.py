@@ -17,7 +17,7 @@ import pytest
 
 import oracle
 import workloads as W
-from parity import column_rel_errors, elementwise_rel_error
+from parity import column_rel_errors, elementwise_rel_error, padding_rows
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -83,10 +83,10 @@ def run(L32, B32, alpha, unit=False, block_size=0, path=0, ldb=None):
     Ld = hs.to_colmajor(L32)
     Bd = hs.to_colmajor(B32, ld=ldb)
     if ldb is not None:
-        Bd.t()[:, B32.shape[0]:] = W.PAD_SENTINEL
+        padding_rows(Bd).fill_(W.PAD_SENTINEL)
     _, rep = hs.trsm(Ld, Bd, alpha, unit=unit, block_size=block_size, path=path, report=True)
     torch.cuda.synchronize()
-    pad = Bd.t()[:, B32.shape[0]:].cpu().numpy() if ldb is not None else None
+    pad = padding_rows(Bd).cpu().numpy() if ldb is not None else None
     return hs.from_colmajor(Bd), rep, pad
 
 

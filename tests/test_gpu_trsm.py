@@ -9,7 +9,7 @@ import pytest
 
 import oracle
 import workloads as W
-from parity import assert_parity
+from parity import assert_parity, padding_rows
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -33,14 +33,13 @@ def run(L, B, alpha, unit=False, block_size=0, path=0, ldb=None, lda=None):
     Bd = hs.to_colmajor(B, ld=ldb)
     if ldb is not None:
         # sentinel in the padding rows
-        store = Bd.t()
-        store[:, B.shape[0]:] = W.PAD_SENTINEL
+        padding_rows(Bd).fill_(W.PAD_SENTINEL)
     _, rep = hs.trsm(Ld, Bd, alpha, unit=unit, block_size=block_size, path=path, report=True)
     torch.cuda.synchronize()
     X = hs.from_colmajor(Bd)
     pad = None
     if ldb is not None:
-        pad = Bd.t()[:, B.shape[0]:].cpu().numpy()
+        pad = padding_rows(Bd).cpu().numpy()
     return X, rep, pad
 
 
@@ -160,12 +159,15 @@ def test_alpha_zero_reads_nothing():
 
 
 def test_padding_rows_untouched():
-    for m, ib in ((37, 0), (150, 32)):
+    # m, n <= 16 take the fused kernel (B staged through LDS), m = 37 the
+    # strip kernel, m = 150 the blocked path
+    for m, n, ib in ((1, 16, 0), (7, 5, 0), (16, 16, 0), (37, 20, 0), (150, 20, 32)):
         for cx in (False, True):
-            L, B = W.problem(9, m, 20, cx)
-            X, _, pad = run(L, B, 1.0, block_size=ib, ldb=m + 11)
+            L, B = W.problem(9, m, n, cx)
+            alpha = complex(0.5, -1.0) if cx else 1.0
+            X, _, pad = run(L, B, alpha, block_size=ib, ldb=m + 11, lda=m + 3)
             assert np.all(pad == W.PAD_SENTINEL), (m, cx)
-            check(L, B, X, 1.0, tag=("pad", m, cx))
+            check(L, B, X, alpha, tag=("pad", m, cx))
 
 
 def test_leading_dimension_of_L():

@@ -11,7 +11,7 @@ import pytest
 
 import oracle
 import workloads as W
-from parity import U, column_rel_errors, elementwise_rel_error
+from parity import U, column_rel_errors, elementwise_rel_error, padding_rows
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -36,10 +36,10 @@ def run(A, B, alpha, side, uplo, trans, unit=False, ldb=None, lda=None):
     Ad = hs.to_colmajor(A, ld=lda)
     Bd = hs.to_colmajor(B, ld=ldb)
     if ldb is not None:
-        Bd.t()[:, B.shape[0]:] = W.PAD_SENTINEL
+        padding_rows(Bd).fill_(W.PAD_SENTINEL)
     hs.trsm_general(Ad, Bd, alpha, side=side, uplo=uplo, trans=trans, unit=unit)
     torch.cuda.synchronize()
-    pad = Bd.t()[:, B.shape[0]:].cpu().numpy() if ldb is not None else None
+    pad = padding_rows(Bd).cpu().numpy() if ldb is not None else None
     return hs.from_colmajor(Bd), pad
 
 
