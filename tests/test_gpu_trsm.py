@@ -198,12 +198,12 @@ def _read_at_offset(buf, m, n, ld, cx):
 
 def test_operands_at_eight_byte_offsets():
     """L and B 8 bytes into their allocations, with odd leading dimensions:
-    the small path's 16-byte accesses (two real rows, one complex element)
-    must read and write exactly the right elements, and leave B's padding
-    rows alone."""
+    the small paths' 16-byte accesses (two real rows, one complex element;
+    the fused kernel for m, n <= 16, the strip kernel above) must read and
+    write exactly the right elements, and leave B's padding rows alone."""
     import ctypes
     for cx in (False, True):
-        for m, n in ((7, 20), (33, 70), (64, 37), (50, 5)):
+        for m, n in ((5, 9), (16, 16), (7, 20), (33, 70), (64, 37), (50, 5)):
             L, B = W.problem(77 + m, m, n, cx)
             lda = m + 2 if m % 2 else m + 1
             ldb = m + 2 if m % 2 else m + 3
