@@ -13,10 +13,9 @@
 // B moves through a small LDS stage (one 16 x 16 block per quarter) so that
 // global loads and stores walk down columns, 16 lanes on one segment; L's
 // rows are read straight into registers.  The walk stops after the largest m
-// among the wavefront's four problems.  Rows at or beyond a
-// problem's m hold a unit diagonal and zero coefficients, so every value
-// stays finite, and they only ever feed rows at or beyond m, which are never
-// stored.  The arithmetic of a problem does not depend on its quarter or
+// among the wavefront's four problems.  Rows at or beyond a problem's m hold
+// a unit diagonal and zero coefficients, so every value stays finite, and
+// they only ever feed rows at or beyond m, which are never stored.  The arithmetic of a problem does not depend on its quarter or
 // launch, and it is the strip kernel's, so a problem gives the same bits
 // alone, in a batch and in a strip.
 
