@@ -115,10 +115,23 @@ __global__ __launch_bounds__(256) void hsma_potrf_base(double *__restrict__ A, i
             }
             __syncthreads();
             const V lij = cj[i];
+            // Slot u holds columns NW u .. NW u + NW - 1 across the
+            // wavefronts: once the loops are unrolled, "all of them beyond
+            // j" and "none of them" are constants, and only the one slot
+            // that straddles j tests this wavefront's column.  Every live
+            // slot's l_cj is read first and the multiply-adds follow, so the
+            // LDS reads overlap instead of waiting one by one.
+            V lc[NU];
+#pragma unroll
+            for (int u = 0; u < NU; ++u)
+                if (NW * u + NW - 1 > j) lc[u] = cj[NW * u + w];
+            __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
             for (int u = 0; u < NU; ++u) {
                 const int c = NW * u + w;
-                if (c > j) r[u] = O::fnms_conj(r[u], lij, cj[c]);
+                const bool all_after = NW * u > j;
+                const bool straddles = !all_after && NW * u + NW - 1 > j;
+                if (all_after || (straddles && c > j)) r[u] = O::fnms_conj(r[u], lij, lc[u]);
             }
         }
     }
