@@ -388,7 +388,7 @@ hsma_status launch_role(GemmParams p, int count, hipStream_t s) {
         if (p.M <= 512) return launch_t<CX, 512, 16, 4, 1, ROLE>(p, count, s);
         return HSMA_NOT_SUPPORTED;
     }
-    if (p.M <= 64 && p.N <= 64) return launch_t<CX, 64, 64, 2, 2, ROLE>(p, count, s);
+    if (p.M <= 64 && p.N <= 64 && ROLE != (int)GemmRole::Update) return launch_t<CX, 64, 64, 2, 2, ROLE>(p, count, s);
     if (ROLE == (int)GemmRole::Herk) {
         // Lower-triangular C: the shape with the fewest rounds of non-empty
         // tiles (tile_choice.h).
@@ -410,7 +410,13 @@ hsma_status launch_role(GemmParams p, int count, hipStream_t s) {
         if (rows128 * ((p.N + HSMA_UPD_BN - 1) / HSMA_UPD_BN) * count >= want)
             return launch_t<CX, HSMA_UPD_BM, HSMA_UPD_BN, HSMA_UPD_WM, HSMA_UPD_WN, ROLE>(p, count, s);
         if (rows128 * ((p.N + 63) / 64) * count >= want) return launch_t<CX, 128, 64, 2, 2, ROLE>(p, count, s);
-        return launch_t<CX, 64, 64, 2, 2, ROLE>(p, count, s);
+        // Fewer still (the thin updates of small solves, e.g. inside a
+        // Cholesky factorization): smaller tiles spread the product over
+        // more CUs.  Each element's K order is the same in every shape.
+        const int64_t rows64 = (p.M + 63) / 64;
+        if (rows64 * ((p.N + 63) / 64) * count >= want) return launch_t<CX, 64, 64, 2, 2, ROLE>(p, count, s);
+        if (rows64 * ((p.N + 31) / 32) * count >= want) return launch_t<CX, 64, 32, 2, 2, ROLE>(p, count, s);
+        return launch_t<CX, 32, 32, 2, 2, ROLE>(p, count, s);
     }
     return launch_t<CX, 128, 128, 2, 2, ROLE>(p, count, s);
 }
