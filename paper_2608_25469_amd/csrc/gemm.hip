@@ -388,7 +388,8 @@ hsma_status launch_role(GemmParams p, int count, hipStream_t s) {
         if (p.M <= 512) return launch_t<CX, 512, 16, 4, 1, ROLE>(p, count, s);
         return HSMA_NOT_SUPPORTED;
     }
-    if (p.M <= 64 && p.N <= 64 && ROLE != (int)GemmRole::Update) return launch_t<CX, 64, 64, 2, 2, ROLE>(p, count, s);
+    if (p.M <= 64 && p.N <= 64 && ROLE != (int)GemmRole::Update && ROLE != (int)GemmRole::Herk)
+        return launch_t<CX, 64, 64, 2, 2, ROLE>(p, count, s);
     if (ROLE == (int)GemmRole::Herk) {
         // Lower-triangular C: the shape with the fewest rounds of non-empty
         // tiles (tile_choice.h).
@@ -397,7 +398,9 @@ hsma_status launch_role(GemmParams p, int count, hipStream_t s) {
         const int best = lower_tile_shape(p.M, p.N, CX, count, cus);
         if (best == 0) return launch_t<CX, 128, 128, 2, 2, ROLE>(p, count, s);
         if (best == 1) return launch_t<CX, 128, 64, 2, 2, ROLE>(p, count, s);
-        return launch_t<CX, 64, 64, 2, 2, ROLE>(p, count, s);
+        if (best == 2) return launch_t<CX, 64, 64, 2, 2, ROLE>(p, count, s);
+        if (best == 3) return launch_t<CX, 64, 32, 2, 2, ROLE>(p, count, s);
+        return launch_t<CX, 32, 32, 2, 2, ROLE>(p, count, s);
     }
     if (ROLE == (int)GemmRole::Update) {
         // The trailing updates of the deepest recursion levels are thin

@@ -28,7 +28,11 @@ struct TileShape {
     int bm, bn;
     double eff;  // throughput relative to 128 x 128
 };
-constexpr TileShape kLowerShapes[3] = {{128, 128, 1.0}, {128, 64, 0.85}, {64, 64, 0.7}};
+// The weights of the two smallest shapes are extrapolated from the others by
+// operand reuse (bm bn / (bm + bn) per staged element: 64, 43, 32, 21, 16).
+constexpr int kNumLowerShapes = 5;
+constexpr TileShape kLowerShapes[kNumLowerShapes] = {
+    {128, 128, 1.0}, {128, 64, 0.85}, {64, 64, 0.7}, {64, 32, 0.5}, {32, 32, 0.35}};
 
 // Tiles of an M x N (real-view) lower-triangular C that hold an element on
 // or below the diagonal; complex C has two real-view rows per row.
@@ -46,7 +50,7 @@ inline int64_t lower_tiles(int64_t M, int64_t N, bool cx, int bm, int bn) {
 inline int lower_tile_shape(int64_t M, int64_t N, bool cx, int count, int64_t cus) {
     int best = 0;
     double best_cost = 0.0;
-    for (int k = 0; k < 3; ++k) {
+    for (int k = 0; k < kNumLowerShapes; ++k) {
         const TileShape &t = kLowerShapes[k];
         const int64_t tiles = lower_tiles(M, N, cx, t.bm, t.bn) * count;
         const int64_t slots = (int64_t)tile_occupancy(t.bm, t.bn) * cus;

@@ -43,7 +43,11 @@ int main() {
         long long M, N;
         bool cx;
         int want;
-    } cases[] = {{8192, 4096, true, 1}, {8192, 8192, false, 1}, {3968, 3968, false, 0}};
+    } cases[] = {{8192, 4096, true, 1}, {8192, 8192, false, 1}, {3968, 3968, false, 0},
+                 // 4096 x 4096 real: three rounds of 64 x 64 tiles beat six of 64 x 32
+                 {4096, 4096, false, 2},
+                 // one round for every shape: the smallest tile (the most CUs busy)
+                 {256, 128, true, 4}, {128, 128, false, 4}};
     for (const Case &c : cases) {
         const int got = lower_tile_shape(c.M, c.N, c.cx, 1, 256);
         if (got != c.want) {
@@ -51,7 +55,8 @@ int main() {
             ++bad;
         }
     }
-    if (tile_occupancy(128, 128) != 2 || tile_occupancy(128, 64) != 3 || tile_occupancy(64, 64) != 3) {
+    if (tile_occupancy(128, 128) != 2 || tile_occupancy(128, 64) != 3 || tile_occupancy(64, 64) != 3 ||
+        tile_occupancy(64, 32) != 3 || tile_occupancy(32, 32) != 3) {
         std::printf("occupancy %d %d %d\n", tile_occupancy(128, 128), tile_occupancy(128, 64), tile_occupancy(64, 64));
         ++bad;
     }

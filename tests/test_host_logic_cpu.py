@@ -1,6 +1,6 @@
 """Host logic of the launches, on the CPU: the bucket order of the grouped
 strip launch (csrc/strip_pack.h) and the tile shape of a lower-triangular
-product (csrc/tile_choice.h).
+product (csrc/tile_choice.h: five shapes, 128 x 128 down to 32 x 32).
 
 Each header is compiled with g++ into a native driver (tests/native/) under
 the address and undefined-behaviour sanitizers: random buckets (every strip
