@@ -182,28 +182,32 @@ hsma_status general_t(hsma_side side, hsma_uplo uplo, hsma_op trans, hsma_diag d
     }
     const GeneralPlan g = plan_general(side, uplo, trans, cx, m, n);
     const int64_t k = g.k, nr = g.nrhs;
-    const size_t a_elems = (size_t)k * k, b_elems = g.in_place ? 0 : (size_t)k * nr;
+    // Without a reversal, a swap or a conjugation the triangle is A's own
+    // lower triangle (the right-side transposed solve of real data, as in a
+    // Cholesky step): the solve reads A where it lies.
+    const bool direct_a = !g.rev && !g.swap_a && !g.conj_a;
+    const size_t a_elems = direct_a ? 0 : (size_t)k * k, b_elems = g.in_place ? 0 : (size_t)k * nr;
     void *ws = nullptr;
-    HSMA_TRY(ws_alloc(&ws, (a_elems + b_elems) * es * sizeof(TC), s));
+    if (a_elems + b_elems > 0) HSMA_TRY(ws_alloc(&ws, (a_elems + b_elems) * es * sizeof(TC), s));
     TC *Ap = static_cast<TC *>(ws);
     TC *Bp = g.in_place ? B : Ap + es * a_elems;
     const int64_t ldbp = g.in_place ? ldb : k;
     const int rev = g.rev ? (kRevI | kRevJ) : 0;
     const int fa = (diag == HSMA_UNIT ? kStrict : kLower) | rev | (g.swap_a ? kSwap : 0) |
                    (g.conj_a ? kConj : 0);
-    hsma_status st = launch_transform<TC>(cx, A, lda, Ap, k, k, k, fa, s);
+    hsma_status st = direct_a ? HSMA_SUCCESS : launch_transform<TC>(cx, A, lda, Ap, k, k, k, fa, s);
     // B' = J B (left, reversed) or J B^T (right)
     const bool left = side == HSMA_LEFT;
     if (st == HSMA_SUCCESS && !g.in_place)
         st = launch_transform<TC>(cx, B, ldb, Bp, k, k, nr, (g.rev ? kRevI : 0) | (left ? 0 : kSwap), s);
     if (st == HSMA_SUCCESS)
-        st = trsm_impl(diag, k, nr, alpha, Ap, k, Bp, ldbp, dtype, 0, 0, s, nullptr, nullptr,
-                       nullptr, nullptr);
+        st = trsm_impl(diag, k, nr, alpha, direct_a ? A : Ap, direct_a ? lda : k, Bp, ldbp, dtype, 0, 0, s,
+                       nullptr, nullptr, nullptr, nullptr);
     // B = J B' (left) or B(r, c) = B'(p(c), r) (right)
     if (st == HSMA_SUCCESS && !g.in_place)
         st = launch_transform<TC>(cx, Bp, k, B, ldb, m, n,
                                   left ? (g.rev ? kRevI : 0) : (kSwap | (g.rev ? kRevJ : 0)), s);
-    hsma_status st2 = ws_free(ws, s);
+    hsma_status st2 = ws ? ws_free(ws, s) : HSMA_SUCCESS;
     return st != HSMA_SUCCESS ? st : st2;
 }
 
