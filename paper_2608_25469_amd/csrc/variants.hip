@@ -182,10 +182,15 @@ hsma_status general_t(hsma_side side, hsma_uplo uplo, hsma_op trans, hsma_diag d
     }
     const GeneralPlan g = plan_general(side, uplo, trans, cx, m, n);
     const int64_t k = g.k, nr = g.nrhs;
-    // Without a reversal, a swap or a conjugation the triangle is A's own
-    // lower triangle (the right-side transposed solve of real data, as in a
-    // Cholesky step): the solve reads A where it lies.
-    const bool direct_a = !g.rev && !g.swap_a && !g.conj_a;
+    // Without a reversal or a swap the triangle is A's own lower triangle (the
+    // right-side transposed solve, as in a Cholesky step), and the solve reads
+    // A where it lies.  A conjugation then moves to B and alpha, which are
+    // copied anyway: X A^H = alpha B is A X^H = conj(alpha) B^H.  Conjugation
+    // is exact, so the result is the same either way.
+    const bool direct_a = !g.rev && !g.swap_a;
+    const bool conj_b = direct_a && g.conj_a;
+    const TC alpha_c[2] = {(TC)al.re, (TC)-al.im};
+    const void *alpha_s = conj_b ? static_cast<const void *>(alpha_c) : alpha;
     const size_t a_elems = direct_a ? 0 : (size_t)k * k, b_elems = g.in_place ? 0 : (size_t)k * nr;
     void *ws = nullptr;
     if (a_elems + b_elems > 0) HSMA_TRY(ws_alloc(&ws, (a_elems + b_elems) * es * sizeof(TC), s));
@@ -199,14 +204,17 @@ hsma_status general_t(hsma_side side, hsma_uplo uplo, hsma_op trans, hsma_diag d
     // B' = J B (left, reversed) or J B^T (right)
     const bool left = side == HSMA_LEFT;
     if (st == HSMA_SUCCESS && !g.in_place)
-        st = launch_transform<TC>(cx, B, ldb, Bp, k, k, nr, (g.rev ? kRevI : 0) | (left ? 0 : kSwap), s);
+        st = launch_transform<TC>(cx, B, ldb, Bp, k, k, nr,
+                                  (g.rev ? kRevI : 0) | (left ? 0 : kSwap) | (conj_b ? kConj : 0), s);
     if (st == HSMA_SUCCESS)
-        st = trsm_impl(diag, k, nr, alpha, direct_a ? A : Ap, direct_a ? lda : k, Bp, ldbp, dtype, 0, 0, s,
+        st = trsm_impl(diag, k, nr, alpha_s, direct_a ? A : Ap, direct_a ? lda : k, Bp, ldbp, dtype, 0, 0, s,
                        nullptr, nullptr, nullptr, nullptr);
     // B = J B' (left) or B(r, c) = B'(p(c), r) (right)
     if (st == HSMA_SUCCESS && !g.in_place)
         st = launch_transform<TC>(cx, Bp, k, B, ldb, m, n,
-                                  left ? (g.rev ? kRevI : 0) : (kSwap | (g.rev ? kRevJ : 0)), s);
+                                  (left ? (g.rev ? kRevI : 0) : (kSwap | (g.rev ? kRevJ : 0))) |
+                                      (conj_b ? kConj : 0),
+                                  s);
     hsma_status st2 = ws ? ws_free(ws, s) : HSMA_SUCCESS;
     return st != HSMA_SUCCESS ? st : st2;
 }
