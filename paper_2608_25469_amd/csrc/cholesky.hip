@@ -171,13 +171,11 @@ hsma_status potrf_rec(bool cx, int64_t n, double *A, int64_t lda, double *work, 
     double *A11 = A, *A21 = A + es * n1, *A22 = A + es * (n1 + n1 * lda);
     HSMA_TRY(potrf_rec(cx, n1, A11, lda, work, s));
     // L21 = A21 inv(L11)^H: X L11^H = A21, the right-side conjugate-transpose
-    // TRSM (transpose for real data).
-    const double one[2] = {1.0, 0.0};
-    HSMA_TRY(hsma_trsm_general(HSMA_RIGHT, HSMA_LOWER, cx ? HSMA_OP_C : HSMA_OP_T, HSMA_NON_UNIT, n2,
-                               n1, one, A11, lda, A21, lda, cx ? HSMA_C64F : HSMA_R64F, s));
-    // A22 <- A22 - L21 L21^H on the lower triangle: copy L21^H (n1 x n2) once,
-    // then one product with the lower-triangular store.
-    HSMA_TRY(launch_conj_transpose(cx, A21, lda, work, n1, n1, n2, s));
+    // TRSM (transpose for real data), which also leaves L21^H (n1 x n2) in
+    // work: the right operand of the update.
+    HSMA_TRY(trsm_right_lower_keep(cx, n2, n1, A11, lda, A21, lda, work, s));
+    // A22 <- A22 - L21 L21^H on the lower triangle: one product with the
+    // lower-triangular store.
     GemmBatch one_b;
     HSMA_TRY(launch_gemm(cx, GemmRole::Herk, (int)(es * n2), (int)n2, (int)(es * n1), cplx{-1.0, 0.0},
                          A21, lda, work, es * n1, cplx{1.0, 0.0}, A22, es * lda, 0, one_b, s, 0, 1));

@@ -209,6 +209,11 @@ hsma_status launch_diag_inv_base(bool cplx_, bool unit, int m, int base, int ib,
                                  const float *A, int64_t lda, float *W, hipStream_t s);
 
 // dst (R x C, ldd) = src^H for src C x R (ldsrc); the transpose for real data.
+// X L^H = B for a lower, non-unit L (m x n X and B, n x n L; FP64 real or
+// complex), the solve of a Cholesky step: X overwrites B, and xh (n x m,
+// leading dimension n) receives X^H as well.
+hsma_status trsm_right_lower_keep(bool cx, int64_t m, int64_t n, const double *A, int64_t lda, double *B,
+                                  int64_t ldb, double *xh, hipStream_t s);
 hsma_status launch_conj_transpose(bool cx, const double *src, int64_t ldsrc, double *dst,
                                   int64_t ldd, int64_t R, int64_t C, hipStream_t s);
 

@@ -168,11 +168,13 @@ GeneralPlan plan_general(int side, int uplo, int trans, bool cx, int64_t m, int6
     return g;
 }
 
-// The re-indexed solve of one general case on components TC.
+// The re-indexed solve of one general case on components TC.  `keep`, when
+// given for a case that gathers B (k x nrhs, leading dimension k), takes the
+// place of the workspace copy of B and holds the solved copy afterwards.
 template <typename TC>
 hsma_status general_t(hsma_side side, hsma_uplo uplo, hsma_op trans, hsma_diag diag, int64_t m,
                       int64_t n, const void *alpha, const TC *A, int64_t lda, TC *B, int64_t ldb,
-                      hsma_dtype dtype, hipStream_t s) {
+                      hsma_dtype dtype, hipStream_t s, TC *keep = nullptr) {
     const bool cx = is_complex(dtype);
     const int es = cx ? 2 : 1;
     const cplx al = read_alpha(dtype, alpha);
@@ -191,11 +193,12 @@ hsma_status general_t(hsma_side side, hsma_uplo uplo, hsma_op trans, hsma_diag d
     const bool conj_b = direct_a && g.conj_a;
     const TC alpha_c[2] = {(TC)al.re, (TC)-al.im};
     const void *alpha_s = conj_b ? static_cast<const void *>(alpha_c) : alpha;
-    const size_t a_elems = direct_a ? 0 : (size_t)k * k, b_elems = g.in_place ? 0 : (size_t)k * nr;
+    const bool use_keep = keep && !g.in_place;
+    const size_t a_elems = direct_a ? 0 : (size_t)k * k, b_elems = g.in_place || use_keep ? 0 : (size_t)k * nr;
     void *ws = nullptr;
     if (a_elems + b_elems > 0) HSMA_TRY(ws_alloc(&ws, (a_elems + b_elems) * es * sizeof(TC), s));
     TC *Ap = static_cast<TC *>(ws);
-    TC *Bp = g.in_place ? B : Ap + es * a_elems;
+    TC *Bp = g.in_place ? B : use_keep ? keep : Ap + es * a_elems;
     const int64_t ldbp = g.in_place ? ldb : k;
     const int rev = g.rev ? (kRevI | kRevJ) : 0;
     const int fa = (diag == HSMA_UNIT ? kStrict : kLower) | rev | (g.swap_a ? kSwap : 0) |
@@ -217,6 +220,13 @@ hsma_status general_t(hsma_side side, hsma_uplo uplo, hsma_op trans, hsma_diag d
                                   s);
     hsma_status st2 = ws ? ws_free(ws, s) : HSMA_SUCCESS;
     return st != HSMA_SUCCESS ? st : st2;
+}
+
+hsma_status trsm_right_lower_keep(bool cx, int64_t m, int64_t n, const double *A, int64_t lda, double *B,
+                                  int64_t ldb, double *xh, hipStream_t s) {
+    const double one[2] = {1.0, 0.0};
+    return general_t<double>(HSMA_RIGHT, HSMA_LOWER, cx ? HSMA_OP_C : HSMA_OP_T, HSMA_NON_UNIT, m, n, one, A,
+                             lda, B, ldb, cx ? HSMA_C64F : HSMA_R64F, s, xh);
 }
 
 }  // namespace hsma
